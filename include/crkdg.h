@@ -1,0 +1,269 @@
+/*
+ * crkdg.h -- C ABI of the MI355X (gfx950) library for the per-stage hot path
+ * of the bound-preserving compact-stencil Runge--Kutta discontinuous Galerkin
+ * method (cRKDG) of Liu, Sun and Zhang, arXiv 2412.16002.
+ *
+ * The library advances   d/dt u + div f(u) = 0   (Sec. 1, the conservation
+ * law) on boxes with uniform Cartesian meshes, for one or many independent
+ * instances ("problems") at once.  One time step is the Butcher-form cRKDG
+ * scheme with the scaling limiter after every stage, in the limited form the
+ * paper recommends (Appendix B, "Scheme 1L"):
+ *     u^(i)   = u~^n + dt * a_{i,i-1} * G(u~^(i-1)),   u~^(i)   = L(u^(i)),   i = 2..s
+ *     u^{n+1} = u~^n + dt * sum_i b_i F(u~^(i)),       u~^{n+1} = L(u^{n+1})
+ * with G = -div^loc f (interior traces only, no neighbour data; Sec. 2.1) and
+ * F = -div^DG f with the Lax--Friedrichs flux (Sec. 2.1), the Butcher tables of
+ * Sec. 3.3, the scaling limiters of Sec. 2.2.2 (scalar, Prop. 2.4) and
+ * Sec. 2.2.3 (Euler, density then internal energy), and the adaptive halving
+ * strategy of Sec. 4.1.
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * - All pointers whose name starts with d_ or that live inside crkdg_state are
+ *   DEVICE pointers owned by the caller; the library never frees or allocates
+ *   them, and allocates nothing per call (only the mesh handle and its small
+ *   device tables, created by crkdg_init_mesh and freed by crkdg_free_mesh).
+ * - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *   asynchronously unless an entry point says it synchronises.
+ * - Return value: 0 on success; negative = usage or runtime error
+ *   (CRKDG_E_*), with a message from crkdg_last_error(); positive = numerical
+ *   status (CRKDG_S_*).  Nothing throws, exits or aborts across the ABI.
+ *   Asynchronous HIP faults surface at the next synchronising call.
+ * - Results are deterministic: no floating-point atomics are used for sums.
+ *
+ * State layout (modal Legendre coefficients, structure of arrays)
+ * ---------------------------------------------------------------
+ * Per cell K the DG function of variable v is
+ *     u_v(x) = sum_m c[v][m] * phi_m(xi),  xi = 2 (x - x_K) / dx in [-1, 1]^d,
+ * phi_m(xi) = prod_j P_{e_j(m)}(xi_j) with Legendre polynomials P_n
+ * (P_n(1) = 1, unnormalised), so c[v][0] is the cell average.  Mode order:
+ *   1D and Q^k: e_0 fastest (m = e_0 + (k+1) e_1 + (k+1)^2 e_2);
+ *   P^k (2D/3D total degree <= k): by total degree, then by decreasing e_0,
+ *   then by decreasing e_1, e.g. 2D P^2: (0,0),(1,0),(0,1),(2,0),(1,1),(0,2).
+ * Cells are numbered naturally, x fastest: K = i + n0 (j + n1 l).
+ * A state holds two arrays:
+ *   avg[v][K]        FP64, the cell averages c[v][0];
+ *   hi [v][m-1][K]   modes m >= 1: double (CRKDG_FP64) or float (CRKDG_MIXED).
+ * Several instances are packed one after the other; crkdg_instance_query gives
+ * each instance's element offsets inside avg and hi.
+ * Euler variables are (rho, m_1..m_d, E); gamma-law gas (Sec. 2.2.3).
+ */
+#ifndef CRKDG_H
+#define CRKDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- enumerations ---------------------------------------------------- */
+#define CRKDG_BC_PERIODIC 0
+#define CRKDG_BC_OUTFLOW 1 /* exterior trace = interior trace */
+
+#define CRKDG_SYS_ADVECTION 0 /* f(u) = a u, scalar */
+#define CRKDG_SYS_BURGERS 1   /* f_d(u) = u^2 / 2, scalar */
+#define CRKDG_SYS_EULER 2     /* compressible Euler, d + 2 variables */
+
+#define CRKDG_SPACE_Q 0 /* degree <= k in each variable (1D: P^k) */
+#define CRKDG_SPACE_P 1 /* total degree <= k */
+
+#define CRKDG_FP64 0  /* every mode and all arithmetic in FP64 */
+#define CRKDG_MIXED 1 /* modes >= 1 and transforms/fluxes in FP32; averages,
+                         admissibility checks, limiter theta and the
+                         conservative average update in FP64 */
+
+/* ---- status codes ---------------------------------------------------- */
+#define CRKDG_OK 0
+#define CRKDG_E_ARG (-1)         /* invalid argument */
+#define CRKDG_E_HIP (-2)         /* HIP runtime error */
+#define CRKDG_E_UNSUPPORTED (-3) /* valid problem, combination not built */
+#define CRKDG_E_LAYOUT (-4)      /* buffer sizes / pointers inconsistent */
+#define CRKDG_S_REJECTED 1       /* a stage cell average left the admissible set */
+#define CRKDG_S_DT_UNDERFLOW 2   /* more than max_halvings halvings in one step */
+#define CRKDG_S_NONFINITE 3      /* non-finite values met */
+#define CRKDG_S_DONE 4           /* the instance reached t_end */
+
+/* flag bits written into crkdg_ctl.flags by the stage kernels */
+#define CRKDG_F_AVERAGE 1u   /* a cell average left B (scalar) / B^eps (Euler) */
+#define CRKDG_F_NONFINITE 2u /* a non-finite cell average */
+
+/* ---- problem description -------------------------------------------- */
+typedef struct crkdg_problem {
+  int32_t dim;       /* 1, 2 or 3 */
+  int32_t n[3];      /* cells per direction (entries >= dim ignored) */
+  double lo[3];      /* box corner */
+  double hi[3];      /* opposite corner */
+  int32_t bc[3];     /* CRKDG_BC_* per direction */
+  int32_t system;    /* CRKDG_SYS_* */
+  double vel[3];     /* advection velocity (CRKDG_SYS_ADVECTION) */
+  double gamma;      /* ratio of specific heats (Euler) */
+  double bound_lo;   /* scalar invariant region B = [bound_lo, bound_hi] (Sec. 2.2.2); */
+  double bound_hi;   /*   +-INFINITY disables that side */
+  double eps;        /* Euler admissible set: rho >= eps and rho e >= eps (Sec. 2.2.3) */
+  int32_t k;         /* polynomial degree, 1..3 */
+  int32_t space;     /* CRKDG_SPACE_* */
+  int32_t stages;    /* 2, 3 or 4: the cRKDG schemes of Sec. 3.3 */
+  int32_t precision; /* CRKDG_FP64 or CRKDG_MIXED */
+  int32_t limiter;   /* 1: scaling limiter after every stage; 0: off */
+  double cfl;        /* trial step dt = cfl / sum_d (a0_d / dx_d)   (Sec. 4.1) */
+  int32_t max_halvings; /* bound on halvings within one step (Sec. 4.1) */
+} crkdg_problem;
+
+typedef struct crkdg_mesh crkdg_mesh; /* opaque handle */
+
+typedef struct crkdg_layout {
+  int32_t n_inst;
+  int32_t hi_bytes;   /* bytes of one hi element: 8 (FP64) or 4 (MIXED), same for all instances */
+  int32_t n_slots;    /* state buffers one step needs: max over instances of stages + 1 */
+  int32_t ctl_bytes;  /* bytes of one crkdg_ctl */
+  int64_t avg_elems;  /* doubles in one state's avg array (all instances) */
+  int64_t hi_elems;   /* elements in one state's hi array (all instances) */
+} crkdg_layout;
+
+typedef struct crkdg_instance_layout {
+  int64_t n_cells;
+  int32_t n_modes;    /* M */
+  int32_t n_vars;     /* V */
+  int32_t n_stages;   /* s */
+  int32_t n_vol_pts;  /* (k+1)^d volume Gauss points */
+  int32_t n_sk_pts;   /* points of the limiter set S_K */
+  int32_t pad;
+  int64_t avg_offset; /* element offset of this instance in avg */
+  int64_t hi_offset;  /* element offset of this instance in hi */
+} crkdg_instance_layout;
+
+/* One state: device pointers to the two arrays described above. */
+typedef struct crkdg_state {
+  double *avg;
+  void *hi;
+} crkdg_state;
+
+/* Per-instance time-step controller, in caller-owned DEVICE memory
+ * (n_inst entries of layout.ctl_bytes = sizeof(crkdg_ctl)).  The stage
+ * kernels read dt and the slot index from it and write flags and wave
+ * speeds into it; the controller kernel of crkdg_step updates it.
+ * crkdg_start initialises it; a caller that fills it by hand must set
+ * status = 0 and goal = INT64_MAX, else every kernel skips the instance. */
+typedef struct crkdg_ctl {
+  double t;              /* time of u~^n */
+  double t_end;          /* final time (INFINITY: none) */
+  double dt;             /* trial step of the current attempt */
+  double dt_fixed;       /* > 0: use this step instead of the CFL rule */
+  double a0[3];          /* max wave speed of u~^n per direction over S_K */
+  uint64_t a0_next[3];   /* same for the candidate u~^{n+1}: bits of non-negative doubles */
+  uint32_t flags;        /* CRKDG_F_* raised during the current attempt */
+  int32_t cur;           /* slot holding u~^n (crkdg_step) */
+  int32_t halvings;      /* halvings in the current step */
+  int32_t status;        /* 0 running, else CRKDG_S_DONE / _DT_UNDERFLOW / _NONFINITE */
+  int64_t accepted;      /* accepted steps */
+  int64_t rejected;      /* rejected attempts */
+  int64_t goal;          /* kernels skip the instance once accepted >= goal */
+  int64_t stages_run;    /* executed stages, accepted or not */
+  double dt_last;        /* step size of the last accepted step */
+  int32_t halvings_last; /* halvings the last accepted step needed */
+  int32_t pad;
+} crkdg_ctl;
+
+typedef struct crkdg_step_info {
+  double t;         /* time after the step */
+  double dt;        /* step size taken */
+  int32_t halvings; /* halvings needed in this step */
+  int32_t status;   /* 0 or CRKDG_S_* */
+  int32_t cur;      /* slot that now holds u~^{n+1} */
+  int32_t pad;
+  int64_t accepted, rejected;
+} crkdg_step_info;
+
+/* ---- entry points ----------------------------------------------------- */
+
+/* Thread-local message of the last error (never NULL). */
+const char *crkdg_last_error(void);
+
+/* Validate `n_inst` problems, build the quadrature / basis / S_K tables in
+ * FP64 (Gauss rule of k+1 points per direction, edge weights summing to one,
+ * Prop. 2.1; S_K = Gauss x Gauss--Lobatto points, Prop. 2.2 and Fig. 1),
+ * upload them, and fill *layout.  Synchronous.  Errors: CRKDG_E_ARG for an
+ * invalid problem, CRKDG_E_UNSUPPORTED for a combination not compiled,
+ * CRKDG_E_HIP. */
+int crkdg_init_mesh(const crkdg_problem *problems, int32_t n_inst, crkdg_mesh **out,
+                    crkdg_layout *layout);
+
+/* Free the handle and its device tables (NULL is accepted).  Synchronous. */
+int crkdg_free_mesh(crkdg_mesh *mesh);
+
+/* Sizes and offsets of instance `inst`. */
+int crkdg_instance_query(const crkdg_mesh *mesh, int32_t inst, crkdg_instance_layout *out);
+
+/* Reference coordinates in [-1,1]^3 (unused coordinates 0) of the points of
+ * instance `inst`: which = 0 volume Gauss points (order used by
+ * crkdg_project, first coordinate fastest), 1 the S_K points.  Writes at most
+ * `cap` points into the host array xyz[cap][3] and their number to *count. */
+int crkdg_points(const crkdg_mesh *mesh, int32_t inst, int32_t which, double *xyz, int32_t cap,
+                 int32_t *count);
+
+/* Discrete L2 projection with the volume Gauss rule (the initial-data
+ * projection): d_samples holds u at the volume Gauss points of every cell,
+ * layout [v][K][q] per instance, instances packed with element offset
+ * avg_offset * n_vol_pts.  Writes the modal state `out`.  The result is not
+ * limited: call crkdg_limit afterwards (the bound-preservation theorem,
+ * Thm. 3.5, assumes a limited u^0). */
+int crkdg_project(crkdg_mesh *mesh, const double *d_samples, crkdg_state out, void *stream);
+
+/* Scaling limiter in place (Prop. 2.4 scalar; Sec. 2.2.3 Euler).  Cell
+ * averages are unchanged.  Cells whose average is outside B / B^eps raise
+ * CRKDG_F_AVERAGE in d_ctl[inst].flags (theta is then clamped to [0,1]).
+ * d_ctl may be NULL (no flags).  Asynchronous. */
+int crkdg_limit(crkdg_mesh *mesh, crkdg_state u, crkdg_ctl *d_ctl, void *stream);
+
+/* Cell averages in natural cell order, d_avg[v][K] per instance (same packing
+ * as a state's avg array; may be NULL), and d_totals[inst][v] = sum_K |K|
+ * ubar_K by a fixed-order tree reduction (may be NULL). Asynchronous. */
+int crkdg_cell_avg(crkdg_mesh *mesh, crkdg_state u, double *d_avg, double *d_totals,
+                   void *stream);
+
+/* CFL wave-speed reduction (Sec. 2.1 definition of a0; Sec. 4.1 trial step):
+ * d_ctl[inst].a0[d] = max over cells and S_K points of the largest |eigenvalue|
+ * of df_d/du at u, and d_ctl[inst].dt = the trial step (or dt_fixed), clipped
+ * to t_end - t.  Asynchronous. */
+int crkdg_cfl(crkdg_mesh *mesh, crkdg_state u, crkdg_ctl *d_ctl, void *stream);
+
+/* Initialise the controllers (host arrays t0, t_end, dt_fixed of n_inst
+ * entries; t_end may be NULL = no end, dt_fixed may be NULL = CFL rule), mark
+ * `slots[cur]` as u~^n, compute a0 and the first trial step from it. The
+ * state must already be limited.  Asynchronous (the host arrays are copied
+ * before return). */
+int crkdg_start(crkdg_mesh *mesh, const crkdg_state *slots, int32_t cur, crkdg_ctl *d_ctl,
+                const double *t0, const double *t_end, const double *dt_fixed, void *stream);
+
+/* One stage from explicit buffers, for stage-level checks.
+ *   stage = 2..s    : out = L(u~^n + dt a_{stage,stage-1} G(u~^(stage-1)))
+ *   stage = s+1     : out = L(u~^n + dt sum_j b_j F(u~^(j)))
+ * states[0] = u~^n, states[j-1] = u~^(j) (j = 2..s); entries the stage does
+ * not read may be anything.  dt = d_ctl[inst].dt.  Sets CRKDG_F_* flags in
+ * d_ctl when an (unlimited) stage average is not admissible (the adaptive
+ * strategy of Sec. 4.1 then rejects the step); on stage s+1 also stores the
+ * wave speeds of the result in d_ctl[inst].a0_next (atomic max).  `out` must
+ * not alias any state the stage reads. Asynchronous. */
+int crkdg_stage(crkdg_mesh *mesh, int32_t stage, const crkdg_state *states, int32_t n_states,
+                crkdg_state out, crkdg_ctl *d_ctl, void *stream);
+
+/* One time step on the slot ring slots[0..layout.n_slots-1] (all instances).
+ * The slot of u~^n is d_ctl[inst].cur; stage j lives in slot (cur + j - 1)
+ * mod (s + 1); on acceptance cur advances by s.  Every step is checked as in
+ * Sec. 4.1: a stage average outside the admissible set rejects the attempt,
+ * halves dt and restarts from the untouched u~^n.
+ *   info == NULL: enqueue ONE attempt for every running instance and return
+ *     without synchronising (graph-capturable; the device controller
+ *     accepts or rejects and computes the next trial dt).
+ *   info != NULL: attempt until every running instance has accepted one step
+ *     (or stopped), synchronising after each attempt; info[inst] receives
+ *     the outcome.  Returns CRKDG_S_DT_UNDERFLOW / CRKDG_S_NONFINITE if any
+ *     instance stopped on that, else 0. */
+int crkdg_step(crkdg_mesh *mesh, const crkdg_state *slots, int32_t n_slots, crkdg_ctl *d_ctl,
+               crkdg_step_info *info, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CRKDG_H */

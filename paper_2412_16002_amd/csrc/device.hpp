@@ -1,0 +1,749 @@
+// Device code of the cRKDG hot path: physics, the element operators G and F,
+// the scaling limiters, and the stage / limiter / CFL / projection kernels.
+//
+// One thread owns one cell.  A cell's modal coefficients are read with fully
+// coalesced loads (cell index fastest in HBM), every contraction is unrolled
+// against the compile-time tables of tables.hpp, and the result is written
+// once.  Inner stages read no neighbour (the compactness of G, Sec. 2.1 and
+// the compactness remark of Sec. 3.2); the final stage reads the face traces
+// of the 2d face neighbours.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+#include <cstdint>
+
+#include "crkdg.h"
+#include "tables.hpp"
+
+namespace crkdg {
+
+constexpr int SYS_ADV = CRKDG_SYS_ADVECTION;
+constexpr int SYS_BURG = CRKDG_SYS_BURGERS;
+constexpr int SYS_EULER = CRKDG_SYS_EULER;
+constexpr int BLOCK = 256;
+constexpr int MAX_SLOTS = 5;
+
+// Per-instance constants, resident in device memory.
+struct InstDev {
+  int64_t ncell;
+  int64_t avg_off;   // element offset inside a state's avg array
+  int64_t hi_off;    // element offset inside a state's hi array
+  int32_t n[3];
+  int32_t bc[3];
+  int32_t stages;
+  int32_t limiter;
+  int32_t max_halvings;
+  int32_t first_block;  // logical block range of this instance
+  int32_t n_blocks;
+  int32_t pad;
+  double rdx[3];     // 1 / dx_d
+  double r2dx[3];    // 2 / dx_d
+  double vel[3];
+  double gamma, blo, bhi, eps, cfl, vol;
+};
+
+// One workgroup = BLOCK consecutive cells of one instance.
+struct BlockItem {
+  int32_t inst;
+  int32_t lblock;    // logical block number (fixed order for reductions)
+  int64_t cell0;
+};
+
+struct Slots {
+  double* avg[MAX_SLOTS];
+  void* hi[MAX_SLOTS];
+  int32_t n;
+  int32_t rotate;    // 1: slot of u~^n is ctl->cur (step ring); 0: slot 0
+};
+
+struct KArgs {
+  const InstDev* inst;
+  const BlockItem* bmap;
+  crkdg_ctl* ctl;      // may be null for limit without flags
+  Slots slots;
+  int32_t stage;       // 2..s+1
+  int32_t pad;
+  double a;            // a_{stage, stage-1}
+  double b[4];         // b_1..b_s (final stage)
+  const double* samples;
+  double* out;         // totals partials / other outputs
+};
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T cmad(double c, T x, T acc) {
+  if (c == 0.0) return acc;
+  if (c == 1.0) return acc + x;
+  if (c == -1.0) return acc - x;
+  return fma(T(c), x, acc);
+}
+
+__device__ __forceinline__ double* sel_avg(const Slots& s, int i) {
+  double* p = s.avg[0];
+#pragma unroll
+  for (int k = 1; k < MAX_SLOTS; ++k)
+    if (i == k) p = s.avg[k];
+  return p;
+}
+__device__ __forceinline__ void* sel_hi(const Slots& s, int i) {
+  void* p = s.hi[0];
+#pragma unroll
+  for (int k = 1; k < MAX_SLOTS; ++k)
+    if (i == k) p = s.hi[k];
+  return p;
+}
+
+__device__ __forceinline__ bool instance_idle(const crkdg_ctl* c) {
+  return c != nullptr && (c->status != 0 || c->accepted >= c->goal);
+}
+
+// raise `bits` in *flags once per wavefront if any lane has `bad`
+__device__ __forceinline__ void raise_flag(uint32_t* flags, bool bad, uint32_t bits) {
+  const unsigned long long m = __ballot(bad);
+  if (m != 0ull && flags != nullptr) {
+    const int lane = threadIdx.x & 63;
+    if (lane == __ffsll(static_cast<long long>(m)) - 1) atomicOr(flags, bits);
+  }
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// physics (Sec. 2.2.3 for Euler)
+// ---------------------------------------------------------------------------
+template <int D, int SYS> struct Phys {
+  static constexpr int V = (SYS == SYS_EULER) ? D + 2 : 1;
+
+  // auxiliary quantities of one state shared by all directions
+  template <typename T> struct Aux {
+    T ir;      // 1 / rho
+    T w[D];    // velocity
+    T p;       // pressure
+  };
+
+  template <typename T>
+  __device__ __forceinline__ static Aux<T> aux(const T* u, const InstDev& I) {
+    Aux<T> a{};
+    if constexpr (SYS == SYS_EULER) {
+      a.ir = T(1) / u[0];
+      T ke = T(0);
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        a.w[j] = u[1 + j] * a.ir;
+        ke = fma(u[1 + j], a.w[j], ke);
+      }
+      a.p = T(I.gamma - 1.0) * (u[D + 1] - T(0.5) * ke);
+    }
+    return a;
+  }
+
+  template <typename T>
+  __device__ __forceinline__ static void flux(const T* u, const Aux<T>& a, int d, const InstDev& I,
+                                              T* f) {
+    if constexpr (SYS == SYS_ADV) {
+      f[0] = T(I.vel[d]) * u[0];
+    } else if constexpr (SYS == SYS_BURG) {
+      f[0] = T(0.5) * u[0] * u[0];
+    } else {
+      f[0] = u[1 + d];
+#pragma unroll
+      for (int j = 0; j < D; ++j) f[1 + j] = u[1 + j] * a.w[d] + (j == d ? a.p : T(0));
+      f[D + 1] = (u[D + 1] + a.p) * a.w[d];
+    }
+  }
+
+  // largest |eigenvalue| of df_d/du
+  template <typename T>
+  __device__ __forceinline__ static T speed(const T* u, const Aux<T>& a, int d, const InstDev& I) {
+    if constexpr (SYS == SYS_ADV) {
+      return T(fabs(I.vel[d]));
+    } else if constexpr (SYS == SYS_BURG) {
+      return fabs(u[0]);
+    } else {
+      return fabs(a.w[d]) + sqrt(T(I.gamma) * a.p * a.ir);
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// the cell kernels of one variant
+// ---------------------------------------------------------------------------
+template <int D, int K, int SP, int SYS, typename T> struct Cell {
+  using S = Space<D, K, SP>;
+  using P = Phys<D, SYS>;
+  static constexpr int V = P::V;
+  static constexpr int M = S::M;
+  static constexpr int MH = M - 1;
+  static constexpr int NS = S::NS;
+  static constexpr bool MIXED = sizeof(T) == 4;
+
+  struct State {
+    double ub[V];     // cell averages (FP64)
+    T ch[V][MH];      // modes >= 1
+  };
+
+  __device__ __forceinline__ static void load(const double* avg, const T* hi, int64_t nc, int64_t c,
+                                              State& s) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) s.ub[v] = avg[v * nc + c];
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int m = 0; m < MH; ++m) s.ch[v][m] = hi[(static_cast<int64_t>(v) * MH + m) * nc + c];
+  }
+
+  __device__ __forceinline__ static void store(double* avg, T* hi, int64_t nc, int64_t c,
+                                               const State& s) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) avg[v * nc + c] = s.ub[v];
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int m = 0; m < MH; ++m) hi[(static_cast<int64_t>(v) * MH + m) * nc + c] = s.ch[v][m];
+  }
+
+  // u at a volume point / face point / S_K point (T arithmetic)
+  __device__ __forceinline__ static void at_vol(const State& s, int q, T* u) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      T a = T(s.ub[v]);
+#pragma unroll
+      for (int m = 1; m < M; ++m) a = cmad(S::tab.phi_v[q][m], s.ch[v][m - 1], a);
+      u[v] = a;
+    }
+  }
+  __device__ __forceinline__ static void at_face(const State& s, int f, int b, T* u) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      T a = T(s.ub[v]);
+#pragma unroll
+      for (int m = 1; m < M; ++m) a = cmad(S::tab.phi_f[f][b][m], s.ch[v][m - 1], a);
+      u[v] = a;
+    }
+  }
+  // S_K values in FP64 (limiter decisions are taken in FP64)
+  __device__ __forceinline__ static double sk_var(const State& s, int p, int v) {
+    double a = 0.0;
+#pragma unroll
+    for (int m = 1; m < M; ++m) a = cmad(S::tab.phi_s[p][m], static_cast<double>(s.ch[v][m - 1]), a);
+    return s.ub[v] + a;
+  }
+
+  struct Acc {
+    double a0[V];     // mode 0 (FP64)
+    T ah[V][MH];      // modes >= 1
+  };
+  __device__ __forceinline__ static void zero(Acc& r) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      r.a0[v] = 0.0;
+#pragma unroll
+      for (int m = 0; m < MH; ++m) r.ah[v][m] = T(0);
+    }
+  }
+
+  // r += scale * [ sum_q sum_d (2/dx_d) wq f_d(u_q) dphi_m/dxi_d ] * prod(2e+1)
+  // (the volume part of the weak form, Sec. 2.1); the mode-0 row is zero.
+  __device__ __forceinline__ static void volume(const State& s, const InstDev& I, double scale,
+                                                Acc& r) {
+    T sd[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) sd[d] = T(scale * I.r2dx[d]);
+#pragma unroll
+    for (int q = 0; q < S::NQ; ++q) {
+      T u[V];
+      at_vol(s, q, u);
+      const auto a = P::aux(u, I);
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        T f[V];
+        P::flux(u, a, d, I, f);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const T g = sd[d] * f[v];
+#pragma unroll
+          for (int m = 1; m < M; ++m) r.ah[v][m - 1] = cmad(S::tab.cvol[q][m][d], g, r.ah[v][m - 1]);
+        }
+      }
+    }
+  }
+
+  // r -= scale / dx_d * sum_b cface[f][b][m] * fn_b  for one face, fn = flux
+  // through the face along +e_d (the sign of the outward normal is in cface).
+  __device__ __forceinline__ static void face_accum(int f, const T (&fn)[S::NFP][V], const InstDev& I,
+                                                    double scale, Acc& r) {
+    const int d = f / 2;
+    const double sc = scale * I.rdx[d];
+    const T sct = T(sc);
+#pragma unroll
+    for (int b = 0; b < S::NFP; ++b)
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        r.a0[v] = cmad(-S::tab.cface[f][b][0], sc * static_cast<double>(fn[b][v]), r.a0[v]);
+        const T g = sct * fn[b][v];
+#pragma unroll
+        for (int m = 1; m < M; ++m) r.ah[v][m - 1] = cmad(-S::tab.cface[f][b][m], g, r.ah[v][m - 1]);
+      }
+  }
+
+  // G = -div^loc f: interior trace flux on every face (Sec. 2.1).
+  __device__ __forceinline__ static void op_local(const State& s, const InstDev& I, double scale,
+                                                  Acc& r) {
+    volume(s, I, scale, r);
+#pragma unroll
+    for (int f = 0; f < S::NF; ++f) {
+      T fn[S::NFP][V];
+#pragma unroll
+      for (int b = 0; b < S::NFP; ++b) {
+        T u[V];
+        at_face(s, f, b, u);
+        const auto a = P::aux(u, I);
+        P::flux(u, a, f / 2, I, fn[b]);
+      }
+      face_accum(f, fn, I, scale, r);
+    }
+  }
+
+  // neighbour across face f of cell c (-1 on an outflow boundary)
+  __device__ __forceinline__ static int64_t neighbour(int64_t c, int f, const InstDev& I) {
+    const int d = f / 2;
+    const int side = (f & 1) ? 1 : -1;
+    int64_t stride = 1;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      if (j < d) stride *= I.n[j];
+    const int64_t i = (c / stride) % I.n[d];
+    int64_t ni = i + side;
+    if (ni < 0 || ni >= I.n[d]) {
+      if (I.bc[d] != CRKDG_BC_PERIODIC) return -1;
+      ni = (ni < 0) ? ni + I.n[d] : ni - I.n[d];
+    }
+    return c + (ni - i) * stride;
+  }
+
+  // F = -div^DG f with the Lax--Friedrichs flux (Sec. 2.1).  Each face flux is
+  // formed in the canonical (lower cell, upper cell) orientation with the same
+  // operation order in both cells, so the two cells of a face see bitwise the
+  // same value and the averages are updated conservatively.
+  __device__ __forceinline__ static void op_dg(const State& s, const double* avg, const T* hi,
+                                               int64_t c, const InstDev& I, double scale, Acc& r) {
+    volume(s, I, scale, r);
+#pragma unroll
+    for (int f = 0; f < S::NF; ++f) {
+      const int d = f / 2;
+      const bool upper = (f & 1) != 0;   // this cell is the lower cell of the face
+      const int64_t nb = neighbour(c, f, I);
+      T ui[S::NFP][V], ue[S::NFP][V];
+#pragma unroll
+      for (int b = 0; b < S::NFP; ++b) at_face(s, f, b, ui[b]);
+      if (nb >= 0) {
+        State sn;
+        load(avg, hi, I.ncell, nb, sn);
+#pragma unroll
+        for (int b = 0; b < S::NFP; ++b) at_face(sn, f ^ 1, b, ue[b]);
+      } else {
+#pragma unroll
+        for (int b = 0; b < S::NFP; ++b)
+#pragma unroll
+          for (int v = 0; v < V; ++v) ue[b][v] = ui[b][v];
+      }
+      // canonical orientation: L = lower cell, R = upper cell
+      T fL[S::NFP][V], fR[S::NFP][V];
+      T alpha = T(0);
+#pragma unroll
+      for (int b = 0; b < S::NFP; ++b) {
+        const T* uL = upper ? ui[b] : ue[b];
+        const T* uR = upper ? ue[b] : ui[b];
+        const auto aL = P::aux(uL, I);
+        const auto aR = P::aux(uR, I);
+        P::flux(uL, aL, d, I, fL[b]);
+        P::flux(uR, aR, d, I, fR[b]);
+        alpha = fmax(alpha, fmax(P::speed(uL, aL, d, I), P::speed(uR, aR, d, I)));
+      }
+      T fn[S::NFP][V];
+#pragma unroll
+      for (int b = 0; b < S::NFP; ++b) {
+        const T* uL = upper ? ui[b] : ue[b];
+        const T* uR = upper ? ue[b] : ui[b];
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+          fn[b][v] = T(0.5) * (fL[b][v] + fR[b][v]) - T(0.5) * alpha * (uR[v] - uL[v]);
+      }
+      face_accum(f, fn, I, scale, r);
+    }
+  }
+
+  // u_out = base + r
+  __device__ __forceinline__ static void combine(const State& base, const Acc& r, State& out) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      out.ub[v] = base.ub[v] + r.a0[v];
+#pragma unroll
+      for (int m = 0; m < MH; ++m) out.ch[v][m] = base.ch[v][m] + r.ah[v][m];
+    }
+  }
+
+  // admissibility of the cell average (Sec. 4.1 algorithm; B^eps by reading A6)
+  __device__ __forceinline__ static bool average_ok(const State& s, const InstDev& I) {
+    if constexpr (SYS == SYS_EULER) {
+      double ke = 0.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) ke = fma(s.ub[1 + j], s.ub[1 + j], ke);
+      const double rhoe = s.ub[D + 1] - 0.5 * ke / s.ub[0];
+      return (s.ub[0] >= I.eps) && (rhoe >= I.eps);
+    } else {
+      return (s.ub[0] >= I.blo) && (s.ub[0] <= I.bhi);
+    }
+  }
+  __device__ __forceinline__ static bool average_finite(const State& s) {
+    bool ok = true;
+#pragma unroll
+    for (int v = 0; v < V; ++v) ok = ok && isfinite(s.ub[v]);
+    return ok;
+  }
+
+  __device__ __forceinline__ static void scale_modes(State& s, double th_first, double th_rest) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const double th = (v == 0) ? th_first : th_rest;
+#pragma unroll
+      for (int m = 0; m < MH; ++m) s.ch[v][m] = T(th * static_cast<double>(s.ch[v][m]));
+    }
+  }
+
+  // every S_K point inside B (scalar) / B^eps (Euler); FP64 evaluation
+  __device__ __forceinline__ static bool points_ok(const State& s, const InstDev& I) {
+    bool ok = true;
+#pragma unroll
+    for (int p = 0; p < NS; ++p) {
+      if constexpr (SYS == SYS_EULER) {
+        const double rho = sk_var(s, p, 0);
+        double ke = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          const double mj = sk_var(s, p, 1 + j);
+          ke = fma(mj, mj, ke);
+        }
+        const double E = sk_var(s, p, D + 1);
+        ok = ok && (rho >= I.eps) && (fma(E, rho, -0.5 * ke) >= I.eps * rho);
+      } else {
+        const double u = sk_var(s, p, 0);
+        ok = ok && (u >= I.blo) && (u <= I.bhi);
+      }
+    }
+    return ok;
+  }
+
+  // Scaling limiter on S_K.  Scalar: Prop. 2.4; Euler: density step then
+  // internal-energy step on the density-limited polynomial (Sec. 2.2.3).
+  // A factor only acts where its bound is violated; it is clamped to [0, 1].
+  __device__ __forceinline__ static void limit(State& s, const InstDev& I) {
+    double th_first = 1.0, th_rest = 1.0;
+    if constexpr (SYS == SYS_EULER) {
+      const double eps = I.eps;
+      const double rb = s.ub[0];
+      double rmin = INFINITY;
+#pragma unroll
+      for (int p = 0; p < NS; ++p) rmin = fmin(rmin, sk_var(s, p, 0));
+      double th1 = 1.0;
+      if (!(rmin >= eps)) {
+        th1 = (rb - eps) / (rb - rmin);
+        th1 = (th1 >= 0.0) ? fmin(th1, 1.0) : 0.0;
+      }
+      // internal energy of the density-limited polynomial: cheap test first
+      bool low = false;
+#pragma unroll
+      for (int p = 0; p < NS; ++p) {
+        const double rho = rb + th1 * (sk_var(s, p, 0) - rb);
+        double ke = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          const double mj = sk_var(s, p, 1 + j);
+          ke = fma(mj, mj, ke);
+        }
+        const double E = sk_var(s, p, D + 1);
+        low = low || !(fma(E, rho, -0.5 * ke) >= eps * rho);
+      }
+      double th2 = 1.0;
+      if (low) {
+        double emin = INFINITY;
+        for (int p = 0; p < NS; ++p) {
+          const double rho = rb + th1 * (sk_var(s, p, 0) - rb);
+          double ke = 0.0;
+          for (int j = 0; j < D; ++j) {
+            const double mj = sk_var(s, p, 1 + j);
+            ke = fma(mj, mj, ke);
+          }
+          emin = fmin(emin, sk_var(s, p, D + 1) - 0.5 * ke / rho);
+        }
+        double kb = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) kb = fma(s.ub[1 + j], s.ub[1 + j], kb);
+        const double eb = s.ub[D + 1] - 0.5 * kb / rb;
+        th2 = (eb - eps) / (eb - emin);
+        th2 = (th2 >= 0.0) ? fmin(th2, 1.0) : 0.0;
+        if (!(emin < eps)) th2 = 1.0;
+      }
+      th_first = th1 * th2;
+      th_rest = th2;
+    } else {
+      const double ub = s.ub[0];
+      double mx = -INFINITY, mn = INFINITY;
+#pragma unroll
+      for (int p = 0; p < NS; ++p) {
+        const double u = sk_var(s, p, 0);
+        mx = fmax(mx, u);
+        mn = fmin(mn, u);
+      }
+      double th = 1.0;
+      if (mx > I.bhi) th = fmin(th, (I.bhi - ub) / (mx - ub));
+      if (mn < I.blo) th = fmin(th, (I.blo - ub) / (mn - ub));
+      th = (th >= 0.0) ? th : 0.0;
+      th_first = th_rest = th;
+    }
+    if (th_first < 1.0 || th_rest < 1.0) {
+      if constexpr (MIXED) {
+        // FP32 rounding of the scaled modes can leave a point a few ulp
+        // outside the bound: re-verify in FP64 and shrink theta by 2^-22,
+        // 2^-18, 2^-14, 2^-10 in turn, finally theta = 0 (exact: the FP64
+        // average is admissible).
+        State orig = s;
+        double f1 = th_first, f2 = th_rest;
+        for (int attempt = 0; attempt < 6; ++attempt) {
+          s = orig;
+          if (attempt == 5) { f1 = 0.0; f2 = 0.0; }
+          scale_modes(s, f1, f2);
+          if (attempt == 5 || points_ok(s, I)) break;
+          const double shrink = 1.0 - ldexp(1.0, -22 + 4 * attempt);
+          f1 *= shrink;
+          f2 *= shrink;
+        }
+      } else {
+        scale_modes(s, th_first, th_rest);
+      }
+    }
+  }
+
+  // max over S_K of the wave speed per direction (FP64)
+  __device__ __forceinline__ static void wave_speeds(const State& s, const InstDev& I, double* a0) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) a0[d] = 0.0;
+#pragma unroll
+    for (int p = 0; p < NS; ++p) {
+      double u[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) u[v] = sk_var(s, p, v);
+      const auto a = P::aux(u, I);
+#pragma unroll
+      for (int d = 0; d < D; ++d) a0[d] = fmax(a0[d], P::speed(u, a, d, I));
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T* hi_ptr(void* p, int64_t off) {
+  return static_cast<T*>(p) + off;
+}
+
+// Inner stage i = 2..s (Scheme 1L): out = L(base + dt a G(in)); flags on a
+// non-admissible unlimited average.
+template <int D, int K, int SP, int SYS, typename T>
+__global__ __launch_bounds__(BLOCK) void k_stage_local(KArgs a) {
+  using C = Cell<D, K, SP, SYS, T>;
+  const BlockItem bi = a.bmap[blockIdx.x];
+  if (bi.inst < 0) return;  // padding entry of the XCD-ordered block map
+  const InstDev& I = a.inst[bi.inst];
+  crkdg_ctl* ctl = a.ctl + bi.inst;
+  if (instance_idle(ctl)) return;
+  const int s = I.stages;
+  const int cur = a.slots.rotate ? ctl->cur : 0;
+  const int nsl = s + 1;
+  const int sl_in = (cur + a.stage - 2) % nsl;
+  const int sl_out = (cur + a.stage - 1) % nsl;
+  const double* in_avg = sel_avg(a.slots, sl_in) + I.avg_off;
+  const T* in_hi = hi_ptr<T>(sel_hi(a.slots, sl_in), I.hi_off);
+  const double* b_avg = sel_avg(a.slots, cur) + I.avg_off;
+  const T* b_hi = hi_ptr<T>(sel_hi(a.slots, cur), I.hi_off);
+  double* o_avg = sel_avg(a.slots, sl_out) + I.avg_off;
+  T* o_hi = hi_ptr<T>(sel_hi(a.slots, sl_out), I.hi_off);
+  const double dt = ctl->dt;
+
+  const int64_t c = bi.cell0 + threadIdx.x;
+  bool bad = false, nonfin = false;
+  if (c < I.ncell) {
+    typename C::State u;
+    C::load(in_avg, in_hi, I.ncell, c, u);
+    typename C::Acc r;
+    C::zero(r);
+    C::op_local(u, I, dt * a.a, r);
+    typename C::State base, out;
+    C::load(b_avg, b_hi, I.ncell, c, base);
+    C::combine(base, r, out);
+    bad = !C::average_ok(out, I);
+    nonfin = !C::average_finite(out);
+    if (I.limiter) C::limit(out, I);
+    C::store(o_avg, o_hi, I.ncell, c, out);
+  }
+  raise_flag(&ctl->flags, bad, CRKDG_F_AVERAGE);
+  raise_flag(&ctl->flags, nonfin, CRKDG_F_NONFINITE);
+}
+
+// Final stage (Scheme 1L): out = L(base + dt sum_j b_j F(u~^(j))); also the
+// wave speeds of the limited result for the next trial step.
+template <int D, int K, int SP, int SYS, typename T>
+__global__ __launch_bounds__(BLOCK) void k_stage_final(KArgs a) {
+  using C = Cell<D, K, SP, SYS, T>;
+  const BlockItem bi = a.bmap[blockIdx.x];
+  if (bi.inst < 0) return;  // padding entry of the XCD-ordered block map
+  const InstDev& I = a.inst[bi.inst];
+  crkdg_ctl* ctl = a.ctl + bi.inst;
+  if (instance_idle(ctl)) return;
+  const int s = I.stages;
+  const int cur = a.slots.rotate ? ctl->cur : 0;
+  const int nsl = s + 1;
+  const int sl_out = (cur + s) % nsl;
+  const double dt = ctl->dt;
+  const double* b_avg = sel_avg(a.slots, cur) + I.avg_off;
+  const T* b_hi = hi_ptr<T>(sel_hi(a.slots, cur), I.hi_off);
+  double* o_avg = sel_avg(a.slots, sl_out) + I.avg_off;
+  T* o_hi = hi_ptr<T>(sel_hi(a.slots, sl_out), I.hi_off);
+
+  const int64_t c = bi.cell0 + threadIdx.x;
+  bool bad = false, nonfin = false;
+  double a0[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) a0[d] = 0.0;
+  if (c < I.ncell) {
+    typename C::Acc r;
+    C::zero(r);
+    typename C::State base;
+    C::load(b_avg, b_hi, I.ncell, c, base);
+    if (a.b[0] != 0.0) C::op_dg(base, b_avg, b_hi, c, I, dt * a.b[0], r);
+#pragma unroll
+    for (int j = 2; j <= 4; ++j) {
+      if (j > s || a.b[j - 1] == 0.0) continue;
+      const int sl = (cur + j - 1) % nsl;
+      const double* j_avg = sel_avg(a.slots, sl) + I.avg_off;
+      const T* j_hi = hi_ptr<T>(sel_hi(a.slots, sl), I.hi_off);
+      typename C::State uj;
+      C::load(j_avg, j_hi, I.ncell, c, uj);
+      C::op_dg(uj, j_avg, j_hi, c, I, dt * a.b[j - 1], r);
+    }
+    typename C::State out;
+    C::combine(base, r, out);
+    bad = !C::average_ok(out, I);
+    nonfin = !C::average_finite(out);
+    if (I.limiter) C::limit(out, I);
+    C::store(o_avg, o_hi, I.ncell, c, out);
+    if (!bad && !nonfin) C::wave_speeds(out, I, a0);
+  }
+  raise_flag(&ctl->flags, bad, CRKDG_F_AVERAGE);
+  raise_flag(&ctl->flags, nonfin, CRKDG_F_NONFINITE);
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const double m = wave_max(a0[d]);
+    if ((threadIdx.x & 63) == 0 && m > 0.0)
+      atomicMax(reinterpret_cast<unsigned long long*>(&ctl->a0_next[d]),
+                static_cast<unsigned long long>(__double_as_longlong(m)));
+  }
+}
+
+// Standalone limiter in place, slot 0.
+template <int D, int K, int SP, int SYS, typename T>
+__global__ __launch_bounds__(BLOCK) void k_limit(KArgs a) {
+  using C = Cell<D, K, SP, SYS, T>;
+  const BlockItem bi = a.bmap[blockIdx.x];
+  if (bi.inst < 0) return;  // padding entry of the XCD-ordered block map
+  const InstDev& I = a.inst[bi.inst];
+  crkdg_ctl* ctl = a.ctl ? a.ctl + bi.inst : nullptr;
+  double* avg = a.slots.avg[0] + I.avg_off;
+  T* hi = hi_ptr<T>(a.slots.hi[0], I.hi_off);
+  const int64_t c = bi.cell0 + threadIdx.x;
+  bool bad = false;
+  if (c < I.ncell) {
+    typename C::State u;
+    C::load(avg, hi, I.ncell, c, u);
+    bad = !C::average_ok(u, I);
+    if (I.limiter) {
+      C::limit(u, I);
+      C::store(avg, hi, I.ncell, c, u);
+    }
+  }
+  if (ctl) raise_flag(&ctl->flags, bad, CRKDG_F_AVERAGE);
+}
+
+// a0 of slot 0 (or of slot ctl->cur when rotate) into ctl->a0_next (atomic max of bits).
+template <int D, int K, int SP, int SYS, typename T>
+__global__ __launch_bounds__(BLOCK) void k_cfl(KArgs a) {
+  using C = Cell<D, K, SP, SYS, T>;
+  const BlockItem bi = a.bmap[blockIdx.x];
+  if (bi.inst < 0) return;  // padding entry of the XCD-ordered block map
+  const InstDev& I = a.inst[bi.inst];
+  crkdg_ctl* ctl = a.ctl + bi.inst;
+  const int cur = a.slots.rotate ? ctl->cur : 0;
+  const double* avg = sel_avg(a.slots, cur) + I.avg_off;
+  const T* hi = hi_ptr<T>(sel_hi(a.slots, cur), I.hi_off);
+  const int64_t c = bi.cell0 + threadIdx.x;
+  double a0[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) a0[d] = 0.0;
+  if (c < I.ncell) {
+    typename C::State u;
+    C::load(avg, hi, I.ncell, c, u);
+    C::wave_speeds(u, I, a0);
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const double m = wave_max(a0[d]);
+    if ((threadIdx.x & 63) == 0 && m > 0.0)
+      atomicMax(reinterpret_cast<unsigned long long*>(&ctl->a0_next[d]),
+                static_cast<unsigned long long>(__double_as_longlong(m)));
+  }
+}
+
+// Discrete L2 projection of point samples at the volume Gauss points.
+template <int D, int K, int SP, int SYS, typename T>
+__global__ __launch_bounds__(BLOCK) void k_project(KArgs a) {
+  using C = Cell<D, K, SP, SYS, T>;
+  using S = typename C::S;
+  const BlockItem bi = a.bmap[blockIdx.x];
+  if (bi.inst < 0) return;  // padding entry of the XCD-ordered block map
+  const InstDev& I = a.inst[bi.inst];
+  double* avg = a.slots.avg[0] + I.avg_off;
+  T* hi = hi_ptr<T>(a.slots.hi[0], I.hi_off);
+  const double* smp = a.samples + I.avg_off * S::NQ;
+  const int64_t c = bi.cell0 + threadIdx.x;
+  if (c >= I.ncell) return;
+  typename C::State u;
+#pragma unroll
+  for (int v = 0; v < C::V; ++v) {
+    double acc[C::M];
+#pragma unroll
+    for (int m = 0; m < C::M; ++m) acc[m] = 0.0;
+#pragma unroll
+    for (int q = 0; q < S::NQ; ++q) {
+      const double x = smp[(v * I.ncell + c) * S::NQ + q];
+#pragma unroll
+      for (int m = 0; m < C::M; ++m)
+        acc[m] = fma(S::pfac(m) * S::tab.wq[q] * S::tab.phi_v[q][m], x, acc[m]);
+    }
+    u.ub[v] = acc[0];
+#pragma unroll
+    for (int m = 1; m < C::M; ++m) u.ch[v][m - 1] = T(acc[m]);
+  }
+  C::store(avg, hi, I.ncell, c, u);
+}
+
+}  // namespace crkdg

@@ -1,0 +1,711 @@
+// Host side of the C ABI declared in include/crkdg.h: validation, layout,
+// variant dispatch, the device step controller and the deterministic totals.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "crkdg.h"
+#include "variants.hpp"
+
+using namespace crkdg;
+
+namespace {
+
+using Registry = int (*)(const VariantOps**);
+const Registry kRegistries[] = {&variants_v1d, &variants_v2d_q_adv, &variants_v2d_p_adv, &variants_v2d_q12_euler, &variants_v2d_q3_euler, &variants_v2d_p_euler, &variants_v3d_q1, &variants_v3d_q2_adv};
+
+thread_local std::string g_err = "";
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(CRKDG_E_HIP, std::string(#expr ": ") + hipGetErrorString(e_));  \
+  } while (0)
+
+// Butcher tables of the cRKDG schemes (Sec. 3.3): only the subdiagonal of A
+// is non-zero for the three schemes.
+struct Butcher {
+  double a[5];  // a[i] = a_{i,i-1}, i = 2..s
+  double b[4];
+};
+Butcher butcher(int s) {
+  Butcher t{};
+  if (s == 2) {
+    t.a[2] = 0.5;
+    t.b[0] = 0.0; t.b[1] = 1.0;
+  } else if (s == 3) {
+    t.a[2] = 1.0 / 3.0; t.a[3] = 2.0 / 3.0;
+    t.b[0] = 0.25; t.b[1] = 0.0; t.b[2] = 0.75;
+  } else {
+    t.a[2] = 0.5; t.a[3] = 0.5; t.a[4] = 1.0;
+    t.b[0] = 1.0 / 6.0; t.b[1] = 1.0 / 3.0; t.b[2] = 1.0 / 3.0; t.b[3] = 1.0 / 6.0;
+  }
+  return t;
+}
+
+const VariantOps* find_ops(int dim, int k, int space, int system, int precision) {
+  const int sp = (dim == 1) ? SP_Q : space;
+  for (Registry r : kRegistries) {
+    const VariantOps* tab = nullptr;
+    const int n = r(&tab);
+    for (int i = 0; i < n; ++i) {
+      const VariantOps& o = tab[i];
+      if (o.dim == dim && o.k == k && o.space == sp && o.system == system && o.precision == precision)
+        return &o;
+    }
+  }
+  return nullptr;
+}
+
+struct Group {
+  const VariantOps* ops;
+  int stages;
+  std::vector<int> insts;
+  int nblocks = 0;              // grid size (a multiple of 8, padded)
+  BlockItem* d_bmap = nullptr;
+};
+
+}  // namespace
+
+struct crkdg_mesh {
+  std::vector<crkdg_problem> probs;
+  std::vector<crkdg_instance_layout> lay;
+  crkdg_layout layout{};
+  std::vector<InstDev> inst;
+  std::vector<Group> groups;
+  InstDev* d_inst = nullptr;
+  double* d_partial = nullptr;  // [total logical blocks][5]
+  int total_lblocks = 0;
+  int max_stages = 0;
+  int device = 0;
+};
+
+namespace {
+
+// Logical blocks of a group in instance-major, cell-ascending order, placed so
+// that hardware dispatch (round-robin over the 8 XCDs) hands each XCD one
+// contiguous run of logical blocks: neighbouring rows of the final stage then
+// meet in the same L2.
+std::vector<BlockItem> xcd_block_map(const std::vector<BlockItem>& logical) {
+  const int nl = static_cast<int>(logical.size());
+  const int nx = 8;
+  const int chunk = (nl + nx - 1) / nx;
+  std::vector<BlockItem> phys(static_cast<size_t>(chunk) * nx, BlockItem{-1, -1, 0});
+  for (int b = 0; b < chunk * nx; ++b) {
+    const int x = b % nx, j = b / nx;
+    const int l = x * chunk + j;
+    if (l < nl) phys[b] = logical[l];
+  }
+  return phys;
+}
+
+int validate(const crkdg_problem& p, int idx) {
+  auto bad = [&](const char* what) {
+    return fail(CRKDG_E_ARG, "problem " + std::to_string(idx) + ": " + what);
+  };
+  if (p.dim < 1 || p.dim > 3) return bad("dim must be 1, 2 or 3");
+  for (int d = 0; d < p.dim; ++d) {
+    if (p.n[d] < 1) return bad("n must be >= 1");
+    if (!(p.hi[d] > p.lo[d])) return bad("hi must exceed lo");
+    if (p.bc[d] != CRKDG_BC_PERIODIC && p.bc[d] != CRKDG_BC_OUTFLOW) return bad("unknown bc");
+  }
+  if (p.system < 0 || p.system > 2) return bad("unknown system");
+  if (p.k < 1 || p.k > 3) return bad("k must be 1..3");
+  if (p.space != CRKDG_SPACE_Q && p.space != CRKDG_SPACE_P) return bad("unknown space");
+  if (p.stages < 2 || p.stages > 4) return bad("stages must be 2, 3 or 4");
+  if (p.precision != CRKDG_FP64 && p.precision != CRKDG_MIXED) return bad("unknown precision");
+  if (p.system == CRKDG_SYS_EULER && !(p.gamma > 1.0)) return bad("gamma must exceed 1");
+  if (p.system == CRKDG_SYS_EULER && !(p.eps > 0.0)) return bad("eps must be positive");
+  if (p.system != CRKDG_SYS_EULER && !(p.bound_lo <= p.bound_hi)) return bad("bound_lo > bound_hi");
+  if (!(p.cfl > 0.0)) return bad("cfl must be positive");
+  if (p.max_halvings < 0) return bad("max_halvings must be >= 0");
+  int64_t nc = 1;
+  for (int d = 0; d < p.dim; ++d) nc *= p.n[d];
+  if (nc > (int64_t(1) << 40)) return bad("too many cells");
+  return CRKDG_OK;
+}
+
+__global__ void k_controller(crkdg_ctl* ctl, const InstDev* inst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  crkdg_ctl& c = ctl[i];
+  const InstDev& I = inst[i];
+  if (c.status != 0 || c.accepted >= c.goal) return;
+  c.stages_run += I.stages;
+  if (c.flags != 0u) {
+    // Sec. 4.1: restart the step from u~^n with half the step size
+    c.rejected += 1;
+    c.halvings += 1;
+    c.flags = 0u;
+    for (int d = 0; d < 3; ++d) c.a0_next[d] = 0ull;
+    if (c.halvings > I.max_halvings) c.status = CRKDG_S_DT_UNDERFLOW;
+    else c.dt *= 0.5;
+    return;
+  }
+  c.accepted += 1;
+  c.dt_last = c.dt;
+  c.halvings_last = c.halvings;
+  c.halvings = 0;
+  c.t = c.t + c.dt;
+  c.cur = (c.cur + I.stages) % (I.stages + 1);
+  double rate = 0.0;
+  bool finite = true;
+  for (int d = 0; d < 3; ++d) {
+    const double a = __longlong_as_double(static_cast<long long>(c.a0_next[d]));
+    c.a0[d] = a;
+    c.a0_next[d] = 0ull;
+    finite = finite && isfinite(a);
+    rate += a * I.rdx[d];
+  }
+  if (!finite) { c.status = CRKDG_S_NONFINITE; return; }
+  if (!(c.t < c.t_end)) { c.status = CRKDG_S_DONE; return; }
+  double dt = (c.dt_fixed > 0.0) ? c.dt_fixed : I.cfl / rate;
+  c.dt = fmin(dt, c.t_end - c.t);
+}
+
+// a0 = a0_next, a0_next = 0, trial dt (Sec. 4.1, reading A2 in several dimensions)
+__global__ void k_a0_finish(crkdg_ctl* ctl, const InstDev* inst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  crkdg_ctl& c = ctl[i];
+  const InstDev& I = inst[i];
+  double rate = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    const double a = __longlong_as_double(static_cast<long long>(c.a0_next[d]));
+    c.a0[d] = a;
+    c.a0_next[d] = 0ull;
+    rate += a * I.rdx[d];
+  }
+  const double dt = (c.dt_fixed > 0.0) ? c.dt_fixed : I.cfl / rate;
+  c.dt = fmin(dt, c.t_end - c.t);
+}
+
+__global__ void k_clear_a0(crkdg_ctl* ctl, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int d = 0; d < 3; ++d) ctl[i].a0_next[d] = 0ull;
+}
+
+__global__ void k_arm(crkdg_ctl* ctl, int n, int disarm) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  ctl[i].goal = disarm ? INT64_MAX : ctl[i].accepted + 1;
+}
+
+// per-block sums of |K| * ubar in a fixed tree order
+__global__ __launch_bounds__(BLOCK) void k_totals_partial(const InstDev* inst, const BlockItem* bmap,
+                                                          const double* avg, double* partial, int V) {
+  const BlockItem bi = bmap[blockIdx.x];
+  if (bi.inst < 0) return;
+  const InstDev& I = inst[bi.inst];
+  __shared__ double sh[BLOCK];
+  const int64_t c = bi.cell0 + threadIdx.x;
+  for (int v = 0; v < V; ++v) {
+    sh[threadIdx.x] = (c < I.ncell) ? I.vol * avg[I.avg_off + v * I.ncell + c] : 0.0;
+    __syncthreads();
+    for (int s = BLOCK / 2; s > 0; s >>= 1) {
+      if (static_cast<int>(threadIdx.x) < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[static_cast<int64_t>(bi.lblock) * 5 + v] = sh[0];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_totals_final(const InstDev* inst, const double* partial,
+                                                        double* totals, int V) {
+  const InstDev& I = inst[blockIdx.x];
+  __shared__ double sh[BLOCK];
+  for (int v = 0; v < V; ++v) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < I.n_blocks; b += BLOCK)
+      s += partial[static_cast<int64_t>(I.first_block + b) * 5 + v];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = BLOCK / 2; k > 0; k >>= 1) {
+      if (static_cast<int>(threadIdx.x) < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x * V + v] = sh[0];
+    __syncthreads();
+  }
+}
+
+int check_mesh(const crkdg_mesh* m) {
+  if (!m) return fail(CRKDG_E_ARG, "mesh is NULL");
+  return CRKDG_OK;
+}
+
+int check_state(const crkdg_state& s, const char* what) {
+  if (!s.avg || !s.hi) return fail(CRKDG_E_ARG, std::string(what) + ": NULL state array");
+  return CRKDG_OK;
+}
+
+KArgs base_args(const crkdg_mesh* m, const Group& g, crkdg_ctl* ctl) {
+  KArgs a{};
+  a.inst = m->d_inst;
+  a.bmap = g.d_bmap;
+  a.ctl = ctl;
+  return a;
+}
+
+int n_vars_of(int system, int dim) { return system == CRKDG_SYS_EULER ? dim + 2 : 1; }
+
+int set_device(const crkdg_mesh* m) {
+  HIP_TRY(hipSetDevice(m->device));
+  return CRKDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* crkdg_last_error(void) { return g_err.c_str(); }
+
+int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** out,
+                    crkdg_layout* layout) {
+  if (!problems || n_inst < 1 || !out || !layout) return fail(CRKDG_E_ARG, "bad arguments");
+  *out = nullptr;
+  for (int i = 0; i < n_inst; ++i) {
+    const int rc = validate(problems[i], i);
+    if (rc) return rc;
+  }
+  const int prec = problems[0].precision;
+  for (int i = 1; i < n_inst; ++i)
+    if (problems[i].precision != prec)
+      return fail(CRKDG_E_ARG, "all instances of a mesh must share one precision");
+
+  auto* m = new crkdg_mesh();
+  m->probs.assign(problems, problems + n_inst);
+  if (hipGetDevice(&m->device) != hipSuccess) {
+    delete m;
+    return fail(CRKDG_E_HIP, "hipGetDevice failed");
+  }
+  std::map<std::tuple<const VariantOps*, int>, int> gidx;
+  int64_t avg_off = 0, hi_off = 0;
+  m->inst.resize(n_inst);
+  m->lay.resize(n_inst);
+  std::vector<std::vector<BlockItem>> logical;
+  int lblock = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    const crkdg_problem& p = problems[i];
+    const VariantOps* ops = find_ops(p.dim, p.k, p.space, p.system, p.precision);
+    if (!ops) {
+      delete m;
+      return fail(CRKDG_E_UNSUPPORTED, "problem " + std::to_string(i) +
+                                           ": no compiled kernel for this dim/k/space/system/precision");
+    }
+    int64_t nc = 1;
+    for (int d = 0; d < p.dim; ++d) nc *= p.n[d];
+    crkdg_instance_layout& L = m->lay[i];
+    L.n_cells = nc;
+    L.n_modes = ops->M;
+    L.n_vars = ops->V;
+    L.n_stages = p.stages;
+    L.n_vol_pts = ops->NQ;
+    L.n_sk_pts = ops->NS;
+    L.avg_offset = avg_off;
+    L.hi_offset = hi_off;
+    avg_off += static_cast<int64_t>(ops->V) * nc;
+    hi_off += static_cast<int64_t>(ops->V) * (ops->M - 1) * nc;
+
+    InstDev& I = m->inst[i];
+    std::memset(&I, 0, sizeof(I));
+    I.ncell = nc;
+    I.avg_off = L.avg_offset;
+    I.hi_off = L.hi_offset;
+    double vol = 1.0;
+    for (int d = 0; d < 3; ++d) {
+      if (d < p.dim) {
+        const double dx = (p.hi[d] - p.lo[d]) / p.n[d];
+        I.n[d] = p.n[d];
+        I.bc[d] = p.bc[d];
+        I.rdx[d] = 1.0 / dx;
+        I.r2dx[d] = 2.0 / dx;
+        I.vel[d] = p.vel[d];
+        vol *= dx;
+      } else {
+        I.n[d] = 1;
+        I.bc[d] = CRKDG_BC_PERIODIC;
+      }
+    }
+    I.vol = vol;
+    I.stages = p.stages;
+    I.limiter = p.limiter;
+    I.max_halvings = p.max_halvings;
+    I.gamma = p.gamma;
+    I.blo = p.bound_lo;
+    I.bhi = p.bound_hi;
+    I.eps = p.eps;
+    I.cfl = p.cfl;
+    m->max_stages = std::max(m->max_stages, p.stages);
+
+    auto key = std::make_tuple(ops, p.stages);
+    auto it = gidx.find(key);
+    int g;
+    if (it == gidx.end()) {
+      g = static_cast<int>(m->groups.size());
+      gidx[key] = g;
+      Group G;
+      G.ops = ops;
+      G.stages = p.stages;
+      m->groups.push_back(G);
+      logical.emplace_back();
+    } else {
+      g = it->second;
+    }
+    m->groups[g].insts.push_back(i);
+    const int64_t nb = (nc + BLOCK - 1) / BLOCK;
+    if (nb + lblock > (int64_t(1) << 30)) {
+      delete m;
+      return fail(CRKDG_E_ARG, "too many cells in total");
+    }
+    I.first_block = lblock;
+    I.n_blocks = static_cast<int>(nb);
+    for (int64_t b = 0; b < nb; ++b) logical[g].push_back(BlockItem{i, lblock + static_cast<int>(b), b * BLOCK});
+    lblock += static_cast<int>(nb);
+  }
+  m->total_lblocks = lblock;
+
+  auto cleanup = [&](const char* what, hipError_t e) {
+    crkdg_free_mesh(m);
+    return fail(CRKDG_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  };
+  hipError_t e;
+  if ((e = hipMalloc(&m->d_inst, sizeof(InstDev) * n_inst)) != hipSuccess) return cleanup("hipMalloc", e);
+  if ((e = hipMemcpy(m->d_inst, m->inst.data(), sizeof(InstDev) * n_inst, hipMemcpyHostToDevice)) != hipSuccess)
+    return cleanup("hipMemcpy", e);
+  if ((e = hipMalloc(&m->d_partial, sizeof(double) * 5 * std::max(1, lblock))) != hipSuccess)
+    return cleanup("hipMalloc", e);
+  for (size_t g = 0; g < m->groups.size(); ++g) {
+    std::vector<BlockItem> phys = xcd_block_map(logical[g]);
+    Group& G = m->groups[g];
+    G.nblocks = static_cast<int>(phys.size());
+    if ((e = hipMalloc(&G.d_bmap, sizeof(BlockItem) * phys.size())) != hipSuccess) return cleanup("hipMalloc", e);
+    if ((e = hipMemcpy(G.d_bmap, phys.data(), sizeof(BlockItem) * phys.size(), hipMemcpyHostToDevice)) != hipSuccess)
+      return cleanup("hipMemcpy", e);
+  }
+
+  crkdg_layout& lo = m->layout;
+  lo.n_inst = n_inst;
+  lo.hi_bytes = (prec == CRKDG_FP64) ? 8 : 4;
+  lo.n_slots = m->max_stages + 1;
+  lo.ctl_bytes = static_cast<int32_t>(sizeof(crkdg_ctl));
+  lo.avg_elems = avg_off;
+  lo.hi_elems = hi_off;
+  *layout = lo;
+  *out = m;
+  return CRKDG_OK;
+}
+
+int crkdg_free_mesh(crkdg_mesh* m) {
+  if (!m) return CRKDG_OK;
+  hipSetDevice(m->device);
+  for (Group& g : m->groups)
+    if (g.d_bmap) hipFree(g.d_bmap);
+  if (m->d_inst) hipFree(m->d_inst);
+  if (m->d_partial) hipFree(m->d_partial);
+  delete m;
+  return CRKDG_OK;
+}
+
+int crkdg_instance_query(const crkdg_mesh* m, int32_t inst, crkdg_instance_layout* out) {
+  if (check_mesh(m)) return CRKDG_E_ARG;
+  if (inst < 0 || inst >= m->layout.n_inst || !out) return fail(CRKDG_E_ARG, "bad instance index");
+  *out = m->lay[inst];
+  return CRKDG_OK;
+}
+
+int crkdg_points(const crkdg_mesh* m, int32_t inst, int32_t which, double* xyz, int32_t cap,
+                 int32_t* count) {
+  if (check_mesh(m)) return CRKDG_E_ARG;
+  if (inst < 0 || inst >= m->layout.n_inst || !count) return fail(CRKDG_E_ARG, "bad arguments");
+  const crkdg_problem& p = m->probs[inst];
+  // reproduce the table order of tables.hpp
+  static const double g2[] = {-0.57735026918962576451, 0.57735026918962576451};
+  static const double g3[] = {-0.77459666924148337704, 0.0, 0.77459666924148337704};
+  static const double g4[] = {-0.86113631159405257522, -0.33998104358485626480,
+                              0.33998104358485626480, 0.86113631159405257522};
+  static const double l2[] = {-1.0, 1.0};
+  static const double l3[] = {-1.0, 0.0, 1.0};
+  const int ng = p.k + 1;
+  const double* g = (ng == 2) ? g2 : (ng == 3) ? g3 : g4;
+  const int nl = (p.k == 1) ? 2 : 3;
+  const double* l = (nl == 2) ? l2 : l3;
+  std::vector<double> pts;
+  if (which == 0) {
+    int nq = 1;
+    for (int d = 0; d < p.dim; ++d) nq *= ng;
+    for (int q = 0; q < nq; ++q) {
+      int r = q;
+      for (int j = 0; j < 3; ++j) {
+        if (j < p.dim) { pts.push_back(g[r % ng]); r /= ng; }
+        else pts.push_back(0.0);
+      }
+    }
+  } else if (which == 1) {
+    int per = nl;
+    for (int d = 0; d < p.dim - 1; ++d) per *= ng;
+    for (int d = 0; d < p.dim; ++d) {
+      for (int c = 0; c < per; ++c) {
+        int r = c;
+        double x[3] = {0.0, 0.0, 0.0};
+        for (int j = 0; j < p.dim; ++j) {
+          if (j == d) { x[j] = l[r % nl]; r /= nl; }
+          else { x[j] = g[r % ng]; r /= ng; }
+        }
+        bool dup = false;
+        for (size_t o = 0; o < pts.size(); o += 3)
+          if (pts[o] == x[0] && pts[o + 1] == x[1] && pts[o + 2] == x[2]) dup = true;
+        if (!dup) pts.insert(pts.end(), x, x + 3);
+      }
+    }
+  } else {
+    return fail(CRKDG_E_ARG, "which must be 0 or 1");
+  }
+  const int n = static_cast<int>(pts.size() / 3);
+  *count = n;
+  if (xyz) {
+    if (cap < n) return fail(CRKDG_E_ARG, "capacity too small");
+    std::memcpy(xyz, pts.data(), sizeof(double) * pts.size());
+  }
+  return CRKDG_OK;
+}
+
+int crkdg_project(crkdg_mesh* m, const double* d_samples, crkdg_state out, void* stream) {
+  if (check_mesh(m)) return CRKDG_E_ARG;
+  if (!d_samples) return fail(CRKDG_E_ARG, "samples is NULL");
+  if (int rc = check_state(out, "out")) return rc;
+  if (int rc = set_device(m)) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (const Group& g : m->groups) {
+    KArgs a = base_args(m, g, nullptr);
+    a.slots.avg[0] = out.avg;
+    a.slots.hi[0] = out.hi;
+    a.samples = d_samples;
+    g.ops->project(a, g.nblocks, s);
+  }
+  HIP_TRY(hipGetLastError());
+  return CRKDG_OK;
+}
+
+int crkdg_limit(crkdg_mesh* m, crkdg_state u, crkdg_ctl* d_ctl, void* stream) {
+  if (check_mesh(m)) return CRKDG_E_ARG;
+  if (int rc = check_state(u, "u")) return rc;
+  if (int rc = set_device(m)) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (const Group& g : m->groups) {
+    KArgs a = base_args(m, g, d_ctl);
+    a.slots.avg[0] = u.avg;
+    a.slots.hi[0] = u.hi;
+    g.ops->limit(a, g.nblocks, s);
+  }
+  HIP_TRY(hipGetLastError());
+  return CRKDG_OK;
+}
+
+int crkdg_cell_avg(crkdg_mesh* m, crkdg_state u, double* d_avg, double* d_totals, void* stream) {
+  if (check_mesh(m)) return CRKDG_E_ARG;
+  if (!u.avg) return fail(CRKDG_E_ARG, "u.avg is NULL");
+  if (int rc = set_device(m)) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (d_avg)
+    HIP_TRY(hipMemcpyAsync(d_avg, u.avg, sizeof(double) * m->layout.avg_elems, hipMemcpyDeviceToDevice, s));
+  if (d_totals) {
+    // instances of different variable counts are reduced per group
+    for (const Group& g : m->groups) {
+      const int V = g.ops->V;
+      hipLaunchKernelGGL(k_totals_partial, dim3(g.nblocks), dim3(BLOCK), 0, s, m->d_inst, g.d_bmap,
+                         u.avg, m->d_partial, V);
+    }
+    HIP_TRY(hipGetLastError());
+    // totals are packed per instance with that instance's V
+    int64_t off = 0;
+    for (int i = 0; i < m->layout.n_inst; ++i) {
+      hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(BLOCK), 0, s, m->d_inst + i, m->d_partial,
+                         d_totals + off, m->lay[i].n_vars);
+      off += m->lay[i].n_vars;
+    }
+    HIP_TRY(hipGetLastError());
+  }
+  return CRKDG_OK;
+}
+
+static int launch_cfl(crkdg_mesh* m, const crkdg_state* slots, int nslots, int rotate, crkdg_ctl* d_ctl,
+                      hipStream_t s) {
+  const int n = m->layout.n_inst;
+  hipLaunchKernelGGL(k_clear_a0, dim3((n + 63) / 64), dim3(64), 0, s, d_ctl, n);
+  for (const Group& g : m->groups) {
+    KArgs a = base_args(m, g, d_ctl);
+    for (int j = 0; j < nslots && j < MAX_SLOTS; ++j) {
+      a.slots.avg[j] = slots[j].avg;
+      a.slots.hi[j] = slots[j].hi;
+    }
+    a.slots.n = nslots;
+    a.slots.rotate = rotate;
+    g.ops->cfl(a, g.nblocks, s);
+  }
+  hipLaunchKernelGGL(k_a0_finish, dim3((n + 63) / 64), dim3(64), 0, s, d_ctl, m->d_inst, n);
+  HIP_TRY(hipGetLastError());
+  return CRKDG_OK;
+}
+
+int crkdg_cfl(crkdg_mesh* m, crkdg_state u, crkdg_ctl* d_ctl, void* stream) {
+  if (check_mesh(m)) return CRKDG_E_ARG;
+  if (int rc = check_state(u, "u")) return rc;
+  if (!d_ctl) return fail(CRKDG_E_ARG, "d_ctl is NULL");
+  if (int rc = set_device(m)) return rc;
+  return launch_cfl(m, &u, 1, 0, d_ctl, static_cast<hipStream_t>(stream));
+}
+
+int crkdg_start(crkdg_mesh* m, const crkdg_state* slots, int32_t cur, crkdg_ctl* d_ctl, const double* t0,
+                const double* t_end, const double* dt_fixed, void* stream) {
+  if (check_mesh(m)) return CRKDG_E_ARG;
+  if (!slots || !d_ctl || !t0) return fail(CRKDG_E_ARG, "NULL argument");
+  const int ns = m->layout.n_slots;
+  if (cur < 0 || cur >= ns) return fail(CRKDG_E_ARG, "cur out of range");
+  for (int j = 0; j < ns; ++j)
+    if (int rc = check_state(slots[j], "slot")) return rc;
+  if (int rc = set_device(m)) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n = m->layout.n_inst;
+  std::vector<crkdg_ctl> h(n);
+  for (int i = 0; i < n; ++i) {
+    std::memset(&h[i], 0, sizeof(crkdg_ctl));
+    h[i].t = t0[i];
+    h[i].t_end = t_end ? t_end[i] : INFINITY;
+    h[i].dt_fixed = dt_fixed ? dt_fixed[i] : 0.0;
+    h[i].cur = cur;
+    h[i].goal = INT64_MAX;
+    if (!(h[i].t < h[i].t_end)) h[i].status = CRKDG_S_DONE;
+  }
+  HIP_TRY(hipMemcpyAsync(d_ctl, h.data(), sizeof(crkdg_ctl) * n, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return launch_cfl(m, slots, ns, 1, d_ctl, s);
+}
+
+static int launch_stage(crkdg_mesh* m, const Group& g, int stage, const Slots& slots, crkdg_ctl* d_ctl,
+                        hipStream_t s) {
+  const Butcher bt = butcher(g.stages);
+  KArgs a = base_args(m, g, d_ctl);
+  a.slots = slots;
+  a.stage = stage;
+  if (stage <= g.stages) {
+    a.a = bt.a[stage];
+    g.ops->stage_local(a, g.nblocks, s);
+  } else {
+    for (int j = 0; j < 4; ++j) a.b[j] = bt.b[j];
+    g.ops->stage_final(a, g.nblocks, s);
+  }
+  return CRKDG_OK;
+}
+
+int crkdg_stage(crkdg_mesh* m, int32_t stage, const crkdg_state* states, int32_t n_states, crkdg_state out,
+                crkdg_ctl* d_ctl, void* stream) {
+  if (check_mesh(m)) return CRKDG_E_ARG;
+  if (!states || !d_ctl) return fail(CRKDG_E_ARG, "NULL argument");
+  if (int rc = check_state(out, "out")) return rc;
+  if (int rc = set_device(m)) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  bool any = false;
+  for (const Group& g : m->groups) {
+    if (stage < 2 || stage > g.stages + 1) continue;
+    // stage 2..s reads u~^(stage-1); the final stage reads u~^(j), b_j != 0
+    const int need = (stage <= g.stages) ? stage - 1 : g.stages;
+    if (n_states < need) return fail(CRKDG_E_ARG, "too few states for this stage");
+    Slots sl{};
+    for (int j = 0; j < need; ++j) {
+      if (int rc = check_state(states[j], "states[j]")) return rc;
+      sl.avg[j] = states[j].avg;
+      sl.hi[j] = states[j].hi;
+      if (states[j].avg == out.avg || states[j].hi == out.hi)
+        return fail(CRKDG_E_ARG, "out aliases an input state");
+    }
+    const int oslot = (stage <= g.stages) ? stage - 1 : g.stages;
+    sl.avg[oslot] = out.avg;
+    sl.hi[oslot] = out.hi;
+    sl.n = g.stages + 1;
+    sl.rotate = 0;
+    launch_stage(m, g, stage, sl, d_ctl, s);
+    any = true;
+  }
+  if (!any) return fail(CRKDG_E_ARG, "stage index out of range for every instance");
+  HIP_TRY(hipGetLastError());
+  return CRKDG_OK;
+}
+
+static int enqueue_attempt(crkdg_mesh* m, const Slots& sl, crkdg_ctl* d_ctl, hipStream_t s) {
+  for (int stage = 2; stage <= m->max_stages + 1; ++stage)
+    for (const Group& g : m->groups)
+      if (stage <= g.stages + 1) launch_stage(m, g, stage, sl, d_ctl, s);
+  const int n = m->layout.n_inst;
+  hipLaunchKernelGGL(k_controller, dim3((n + 63) / 64), dim3(64), 0, s, d_ctl, m->d_inst, n);
+  HIP_TRY(hipGetLastError());
+  return CRKDG_OK;
+}
+
+int crkdg_step(crkdg_mesh* m, const crkdg_state* slots, int32_t n_slots, crkdg_ctl* d_ctl,
+               crkdg_step_info* info, void* stream) {
+  if (check_mesh(m)) return CRKDG_E_ARG;
+  if (!slots || !d_ctl) return fail(CRKDG_E_ARG, "NULL argument");
+  if (n_slots < m->layout.n_slots || n_slots > MAX_SLOTS)
+    return fail(CRKDG_E_LAYOUT, "n_slots must be layout.n_slots");
+  Slots sl{};
+  for (int j = 0; j < n_slots; ++j) {
+    if (int rc = check_state(slots[j], "slot")) return rc;
+    sl.avg[j] = slots[j].avg;
+    sl.hi[j] = slots[j].hi;
+  }
+  sl.n = n_slots;
+  sl.rotate = 1;
+  if (int rc = set_device(m)) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n = m->layout.n_inst;
+  if (!info) return enqueue_attempt(m, sl, d_ctl, s);
+
+  hipLaunchKernelGGL(k_arm, dim3((n + 63) / 64), dim3(64), 0, s, d_ctl, n, 0);
+  std::vector<crkdg_ctl> h(n);
+  int max_attempts = 2;
+  for (const crkdg_problem& p : m->probs) max_attempts = std::max(max_attempts, p.max_halvings + 2);
+  bool done = false;
+  for (int att = 0; att < max_attempts && !done; ++att) {
+    if (int rc = enqueue_attempt(m, sl, d_ctl, s)) return rc;
+    HIP_TRY(hipMemcpyAsync(h.data(), d_ctl, sizeof(crkdg_ctl) * n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    done = true;
+    for (int i = 0; i < n; ++i)
+      if (h[i].status == 0 && h[i].accepted < h[i].goal) done = false;
+  }
+  hipLaunchKernelGGL(k_arm, dim3((n + 63) / 64), dim3(64), 0, s, d_ctl, n, 1);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  int ret = CRKDG_OK;
+  for (int i = 0; i < n; ++i) {
+    crkdg_step_info& o = info[i];
+    std::memset(&o, 0, sizeof(o));
+    o.t = h[i].t;
+    o.dt = h[i].dt_last;
+    o.halvings = h[i].halvings_last;
+    o.status = h[i].status == CRKDG_S_DONE ? 0 : h[i].status;
+    o.cur = h[i].cur;
+    o.accepted = h[i].accepted;
+    o.rejected = h[i].rejected;
+    if (h[i].status == CRKDG_S_DT_UNDERFLOW || h[i].status == CRKDG_S_NONFINITE) ret = h[i].status;
+  }
+  return ret;
+}
+
+}  // extern "C"

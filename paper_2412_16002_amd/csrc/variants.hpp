@@ -1,0 +1,51 @@
+// Launchers of the templated kernels, one table per compiled variant
+// (dimension, degree, space, system, precision).
+#pragma once
+
+#include "device.hpp"
+
+namespace crkdg {
+
+using Launch = void (*)(const KArgs&, int nblocks, hipStream_t);
+
+struct VariantOps {
+  int dim, k, space, system, precision;
+  int M, V, NQ, NS;
+  Launch stage_local, stage_final, limit, cfl, project;
+};
+
+template <int D, int K, int SP, int SYS, typename T> struct Ops {
+  using C = Cell<D, K, SP, SYS, T>;
+  static void stage_local(const KArgs& a, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((k_stage_local<D, K, SP, SYS, T>), dim3(nb), dim3(BLOCK), 0, s, a);
+  }
+  static void stage_final(const KArgs& a, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((k_stage_final<D, K, SP, SYS, T>), dim3(nb), dim3(BLOCK), 0, s, a);
+  }
+  static void limit(const KArgs& a, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((k_limit<D, K, SP, SYS, T>), dim3(nb), dim3(BLOCK), 0, s, a);
+  }
+  static void cfl(const KArgs& a, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((k_cfl<D, K, SP, SYS, T>), dim3(nb), dim3(BLOCK), 0, s, a);
+  }
+  static void project(const KArgs& a, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((k_project<D, K, SP, SYS, T>), dim3(nb), dim3(BLOCK), 0, s, a);
+  }
+  static VariantOps make() {
+    return VariantOps{D, K, SP, SYS, sizeof(T) == 8 ? CRKDG_FP64 : CRKDG_MIXED,
+                      C::M, C::V, C::S::NQ, C::NS,
+                      &stage_local, &stage_final, &limit, &cfl, &project};
+  }
+};
+
+// per-translation-unit registries (defined in variants_*.hip)
+int variants_v1d(const VariantOps** out);
+int variants_v2d_q_adv(const VariantOps** out);
+int variants_v2d_p_adv(const VariantOps** out);
+int variants_v2d_q12_euler(const VariantOps** out);
+int variants_v2d_q3_euler(const VariantOps** out);
+int variants_v2d_p_euler(const VariantOps** out);
+int variants_v3d_q1(const VariantOps** out);
+int variants_v3d_q2_adv(const VariantOps** out);
+
+}  // namespace crkdg

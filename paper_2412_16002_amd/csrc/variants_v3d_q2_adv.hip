@@ -1,0 +1,12 @@
+// Compiled variants: 3D Q^2 advection; FP64 and mixed precision.
+#include "variants.hpp"
+
+namespace crkdg {
+static const VariantOps kOps[] = {
+    Ops<3, 2, SP_Q, SYS_ADV, double>::make(), Ops<3, 2, SP_Q, SYS_ADV, float>::make(),
+};
+int variants_v3d_q2_adv(const VariantOps** out) {
+  *out = kOps;
+  return static_cast<int>(sizeof(kOps) / sizeof(kOps[0]));
+}
+}  // namespace crkdg
