@@ -1,0 +1,240 @@
+"""Benchmark of the cRKDG hot path on one MI355X.
+
+Workload: 2D compressible Euler on a periodic 1024 x 1024 mesh, tensor Q^2
+modal DG (9 modes x 4 variables), 3-stage cRKDG (Heun's third-order method)
+with the limiter after every stage, seeded 64-site Voronoi states
+(rho in [1e-3, 1], p in [1e-6, 10], |w| <= 3).  One step = all stages
+(local stages with G, final stage with F and Lax--Friedrichs fluxes, the
+scaling limiter after each, the fused CFL wave-speed maximum) plus the device
+step controller, for the whole mesh.
+
+The headline `value` is the mixed-precision form (FP32 modes >= 1, FP64
+averages / checks / limiter theta / average update); the plain FP64 form is
+timed on the same workload and reported beside it with the relative L1
+difference of the two after the same number of steps.
+
+Metric: DOF-stage updates/s = Nc * M * V * executed stages / wall time, with
+the state resident in HBM before the timed region starts.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=1024, help="cells per direction")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (to scale HBM byte counters)")
+    return ap.parse_args()
+
+
+def state_bytes(nvars, nmodes, mixed):
+    return nvars * (8 + (4 if mixed else 8) * (nmodes - 1))
+
+
+def setup(case, precision, crkdg, torch):
+    params = dict(case.params, precision=precision)
+    mesh = crkdg.Mesh(crkdg.problem_from_params(params))
+    slots = mesh.new_slots()
+    a, h = mesh.views(slots[0])
+    a.copy_(torch.from_numpy(case.cell_states.T.copy()))
+    h.zero_()
+    ctl = mesh.new_ctl()
+    mesh.limit(slots[0], ctl)
+    mesh.start(slots, ctl)
+    torch.cuda.synchronize()
+    return mesh, slots, ctl
+
+
+def run_steps(mesh, slots, ctl, k, torch, stream):
+    """k asynchronous attempts (one crkdg_step each); returns elapsed ms from
+    HIP events on the stream the kernels run on."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(k):
+        mesh.step(slots, ctl, sync=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def time_kernels(mesh, slots, ctl, reps, torch, stream):
+    """Average duration (ms) of each stage kernel, launched alone through
+    crkdg_stage on the same buffers, timed with HIP events on its stream."""
+    s = mesh.problems[0].stages
+    c = mesh.ctl_read(ctl)[0]
+    cur = c["cur"]
+    n = len(slots)
+    states = [slots[(cur + j) % n] for j in range(s)]
+    out = slots[(cur + s) % n]
+    mesh.ctl_write(ctl, [{"dt": c["dt"], "cur": 0}])
+    res = {}
+    for i in range(2, s + 2):
+        o = out if i == s + 1 else slots[(cur + i - 1) % n]
+        mesh.stage(i, states, o, ctl)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            mesh.stage(i, states, o, ctl)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[i] = e0.elapsed_time(e1) / reps
+    return res
+
+
+def cpu_baseline(case, budget_s=20.0):
+    """The oracle, as it is, on a bounded sample of the same workload: a
+    periodic 96 x 96 sub-mesh with the same kind of data, one step at a time
+    until ~budget_s of CPU time, single thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+    from paper_2412_16002_amd import inputs
+    from tests._helpers import oracle_problem
+
+    n = 96
+    sub = inputs.euler_2d_voronoi(seed=0, n=n)
+    params = dict(case.params, n=(n, n))
+    with threadpool_limits(limits=1):
+        o = oracle.CRKDG(oracle_problem(params))
+        U = o.constant_state(sub.cell_states)
+        U = o.limit(U)[0]
+        t0 = time.perf_counter()
+        steps = 0
+        stages = 0
+        t = 0.0
+        while time.perf_counter() - t0 < budget_s or steps == 0:
+            U, info = o.step(U, t)
+            t = info["t"]
+            steps += 1
+            stages += o.p.stages * (info["halvings"] + 1)
+        el = time.perf_counter() - t0
+    dof = o.ncell * o.M * o.V
+    return {"value": dof * stages / el, "unit": "DOF-stage updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"periodic {n}x{n} sub-mesh of the same 2D Euler Q2 Voronoi workload, "
+                      f"{steps} full steps in {el:.1f} s, FP64 numpy, 1 thread"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design "
+                                   "note (see the design document), not an implemented path",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2412_16002_amd import crkdg, inputs
+
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 3}), flush=True)
+        return
+    stream = torch.cuda.current_stream()
+    case = inputs.euler_2d_voronoi(seed=0, n=args.n)
+    Nc = args.n * args.n
+    M, V, s = 9, 4, 3
+    dof = Nc * M * V
+
+    results = {}
+    finals = {}
+    for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):
+        mesh, slots, ctl = setup(case, prec, crkdg, torch)
+        run_steps(mesh, slots, ctl, args.warmup, torch, stream)
+        c0 = mesh.ctl_read(ctl)[0]
+        ms = run_steps(mesh, slots, ctl, args.steps, torch, stream)
+        c1 = mesh.ctl_read(ctl)[0]
+        stages_run = c1["stages_run"] - c0["stages_run"]
+        accepted = c1["accepted"] - c0["accepted"]
+        rejected = c1["rejected"] - c0["rejected"]
+        kern = time_kernels(mesh, slots, ctl, args.kernel_reps, torch, stream)
+        finals[prec] = (mesh, slots, c1)
+        results[prec] = dict(ms=ms, stages_run=stages_run, accepted=accepted, rejected=rejected,
+                             kern=kern, t=c1["t"], status=c1["status"])
+
+    mixed = results["mixed"]
+    value = dof * mixed["stages_run"] / (mixed["ms"] / 1e3)
+    S = state_bytes(V, M, True)
+    # dominant kernel: the final stage (reads u~^n and u~^(3), writes u~^{n+1})
+    kfin = mixed["kern"][s + 1]
+    alg_bytes = 3 * S * Nc
+    achieved = alg_bytes / (kfin / 1e3) / 1e9
+    step_bytes = 8 * S * Nc   # Heun3 Scheme 1L: 2S + 3S + 3S per step
+    line = {
+        "metric": "DOF-stage updates/s",
+        "value": value,
+        "unit": "DOF-stage updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": mixed["ms"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic (seeded 64-site Voronoi states)",
+        "config": {"workload": f"2D Euler Q2 modal DG, {args.n}x{args.n} periodic, 3-stage cRKDG "
+                               f"(Heun3) + scaling limiter, mixed precision",
+                   "cells": Nc, "modes": M, "vars": V, "stages": s, "dof": dof},
+        "accepted_steps": mixed["accepted"],
+        "rejected_attempts": mixed["rejected"],
+        "kernel_ms": {f"stage{i}": v for i, v in mixed["kern"].items()},
+        "step_hbm_fraction": (step_bytes / (mixed["ms"] / args.steps / 1e3) / 1e9) / HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_stage_final<2,2,Q,Euler,float>",
+                     "alg_bytes_per_launch": alg_bytes},
+    }
+    if "fp64" in results:
+        f = results["fp64"]
+        v64 = dof * f["stages_run"] / (f["ms"] / 1e3)
+        line["fp64"] = {"value": v64, "ms_per_step": f["ms"] / args.steps,
+                        "kernel_ms": {f"stage{i}": v for i, v in f["kern"].items()},
+                        "accepted_steps": f["accepted"], "rejected_attempts": f["rejected"]}
+        line["speedup_mixed_vs_fp64"] = value / v64
+        # relative L1 difference of the cell averages after the same number of attempts
+        mm, ms_, cm = finals["mixed"]
+        mf, sf, cf = finals["fp64"]
+        am, _ = mm.views(ms_[cm["cur"]])
+        af, _ = mf.views(sf[cf["cur"]])
+        diff = (am - af).abs().sum(dim=1) / af.abs().sum(dim=1)
+        line["l1_rel_avg_mixed_vs_fp64"] = float(diff.max())
+        line["t_mixed_vs_fp64"] = [cm["t"], cf["t"]]
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(case)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -154,6 +154,28 @@ class Problem:
         return p
 
 
+_SYS_NAMES = {"advection": SYS_ADVECTION, "burgers": SYS_BURGERS, "euler": SYS_EULER}
+_BC_NAMES = {"periodic": BC_PERIODIC, "outflow": BC_OUTFLOW}
+
+
+def problem_from_params(params: dict) -> Problem:
+    """Problem from a workload parameter dict (names as in crkdg_problem,
+    enumerations spelled as words: system 'euler', space 'Q', bc 'periodic',
+    precision 'fp64' / 'mixed')."""
+    d = params["dim"]
+    bc = tuple(_BC_NAMES[b] for b in params.get("bc", ("periodic",) * d)) + (BC_PERIODIC,) * (3 - d)
+    n = tuple(params["n"]) + (1,) * (3 - d)
+    return Problem(
+        dim=d, n=n, system=_SYS_NAMES[params["system"]], k=params["k"],
+        space=SPACE_Q if params.get("space", "Q") == "Q" else SPACE_P, stages=params["stages"],
+        precision=FP64 if params.get("precision", "fp64") == "fp64" else MIXED,
+        lo=tuple(params.get("lo", (0.0, 0.0, 0.0))), hi=tuple(params.get("hi", (1.0, 1.0, 1.0))),
+        bc=bc, vel=tuple(params.get("vel", (1.0, 1.0, 1.0))), gamma=params.get("gamma", 1.4),
+        bound_lo=params.get("bound_lo", -math.inf), bound_hi=params.get("bound_hi", math.inf),
+        eps=params.get("eps", 1e-8), limiter=int(params.get("limiter", True)),
+        cfl=params.get("cfl", 0.1), max_halvings=params.get("max_halvings", 40))
+
+
 class State:
     """A state: avg (FP64) and hi (FP64 or FP32) flat device tensors."""
 

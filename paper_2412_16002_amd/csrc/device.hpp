@@ -38,19 +38,39 @@ struct InstDev {
   int32_t max_halvings;
   int32_t first_block;  // logical block range of this instance
   int32_t n_blocks;
-  int32_t pad;
+  int32_t dim;
   double rdx[3];     // 1 / dx_d
   double r2dx[3];    // 2 / dx_d
   double vel[3];
   double gamma, blo, bhi, eps, cfl, vol;
 };
 
-// One workgroup = BLOCK consecutive cells of one instance.
+// One workgroup = one tile of cells of one instance: BLOCK consecutive cells
+// in 1D, a TILE_X x TILE_Y tile of one x-y plane in 2D/3D (a wavefront then
+// covers TILE_X x 64/TILE_X cells: full 128-byte row segments of the FP32
+// arrays, both face neighbours close, and fewer wavefronts crossed by a
+// discontinuity than with 64-cell row segments).
 struct BlockItem {
   int32_t inst;
   int32_t lblock;    // logical block number (fixed order for reductions)
-  int64_t cell0;
+  int32_t x0, y0;    // tile origin (1D: first cell)
+  int32_t z, pad;
 };
+constexpr int TILE_X = 32;
+constexpr int TILE_Y = BLOCK / TILE_X;
+
+__device__ __forceinline__ int64_t tile_cell(const BlockItem& bi, int dim, const int32_t* n,
+                                             int64_t ncell, bool& active) {
+  if (dim == 1) {
+    const int64_t c = static_cast<int64_t>(bi.x0) + threadIdx.x;
+    active = c < ncell;
+    return c;
+  }
+  const int x = bi.x0 + static_cast<int>(threadIdx.x % TILE_X);
+  const int y = bi.y0 + static_cast<int>(threadIdx.x / TILE_X);
+  active = x < n[0] && y < n[1];
+  return x + static_cast<int64_t>(n[0]) * (y + static_cast<int64_t>(n[1]) * bi.z);
+}
 
 struct Slots {
   double* avg[MAX_SLOTS];
@@ -70,6 +90,8 @@ struct KArgs {
   double b[4];         // b_1..b_s (final stage)
   const double* samples;
   double* out;         // totals partials / other outputs
+  int2* queue;         // cells whose limiter is deferred (instance, cell)
+  unsigned* qcount;    // number of queued cells of this stage
 };
 
 // ---------------------------------------------------------------------------
@@ -111,6 +133,19 @@ __device__ __forceinline__ void raise_flag(uint32_t* flags, bool bad, uint32_t b
   }
 }
 
+// 1/x: FP32 uses the hardware reciprocal (1 ulp); FP64 refines the hardware
+// estimate with two Newton--Raphson steps r <- r (2 - x r).  Deterministic,
+// so both cells of a face still compute bitwise the same flux.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = r * fma(-x, r, 2.0);
+  r = r * fma(-x, r, 2.0);
+  return r;
+}
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fsqrt(double x) { return sqrt(x); }
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
@@ -134,7 +169,7 @@ template <int D, int SYS> struct Phys {
   __device__ __forceinline__ static Aux<T> aux(const T* u, const InstDev& I) {
     Aux<T> a{};
     if constexpr (SYS == SYS_EULER) {
-      a.ir = T(1) / u[0];
+      a.ir = recip(u[0]);
       T ke = T(0);
 #pragma unroll
       for (int j = 0; j < D; ++j) {
@@ -169,7 +204,7 @@ template <int D, int SYS> struct Phys {
     } else if constexpr (SYS == SYS_BURG) {
       return fabs(u[0]);
     } else {
-      return fabs(a.w[d]) + sqrt(T(I.gamma) * a.p * a.ir);
+      return fabs(a.w[d]) + fsqrt(T(I.gamma) * a.p * a.ir);
     }
   }
 };
@@ -443,10 +478,128 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
     return ok;
   }
 
-  // Scaling limiter on S_K.  Scalar: Prop. 2.4; Euler: density step then
-  // internal-energy step on the density-limited polynomial (Sec. 2.2.3).
-  // A factor only acts where its bound is violated; it is clamped to [0, 1].
-  __device__ __forceinline__ static void limit(State& s, const InstDev& I) {
+  // One pass over S_K for the common case.  Returns true when every S_K
+  // point is inside B (scalar) / B^eps (Euler) -- then the limiter is the
+  // identity, exactly as the FP64 algorithm decides -- and, with A0, folds the
+  // wave speeds of the points into a0[].  FP64: the exact tests of the
+  // limiter.  Mixed: FP32 evaluation with a rigorous bound on its rounding
+  // error (each value is a sum of at most M terms bounded by
+  // B = |ubar| + sum |c_m|, since |phi_m| <= 1 on the cell), so "pass" in FP32
+  // implies "pass" in FP64; near the bounds the FP64 limiter decides.
+  template <bool A0>
+  __device__ __forceinline__ static bool sk_pass(const State& s, const InstDev& I, double* a0) {
+    T ub[V], err[V], bnd[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      ub[v] = T(s.ub[v]);
+      if constexpr (MIXED) {
+        T b = fabs(ub[v]);
+#pragma unroll
+        for (int m = 0; m < MH; ++m) b += fabs(s.ch[v][m]);
+        bnd[v] = b;
+        err[v] = T(2.0 * (M + 1) * 0x1p-24) * b;
+      } else {
+        bnd[v] = T(0);
+        err[v] = T(0);
+      }
+    }
+    bool ok = true;
+    if constexpr (SYS == SYS_EULER) {
+      T thr_rho = T(I.eps) + T(2) * err[0];
+      T marg = T(0);
+      if constexpr (MIXED) {
+        T mm = bnd[D + 1] * err[0] + bnd[0] * err[D + 1];
+        T bb = bnd[D + 1] * bnd[0];
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+          mm += bnd[1 + j] * err[1 + j];
+          bb += bnd[1 + j] * bnd[1 + j];
+        }
+        marg = T(2) * (mm + T(4 * 0x1p-24) * bb) + T(2 * I.eps) * err[0];
+        thr_rho *= T(1 + 0x1p-20);
+      }
+      const T eps = T(I.eps);
+#pragma unroll
+      for (int p = 0; p < NS; ++p) {
+        T u[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          T a = ub[v];
+#pragma unroll
+          for (int m = 1; m < M; ++m) a = cmad(S::tab.phi_s[p][m], s.ch[v][m - 1], a);
+          u[v] = a;
+        }
+        T ke = T(0);
+#pragma unroll
+        for (int j = 0; j < D; ++j) ke = fma(u[1 + j], u[1 + j], ke);
+        const T q = fma(u[D + 1], u[0], T(-0.5) * ke);
+        T rhs = fma(eps, u[0], marg);
+        if constexpr (MIXED) rhs *= T(1 + 0x1p-20);
+        ok = ok && (u[0] >= thr_rho) && (q >= rhs);
+        if constexpr (A0) {
+          const auto ax = P::aux(u, I);
+#pragma unroll
+          for (int d = 0; d < D; ++d) a0[d] = fmax(a0[d], static_cast<double>(P::speed(u, ax, d, I)));
+        }
+      }
+    } else {
+      const double lo = I.blo, hi = I.bhi;
+#pragma unroll
+      for (int p = 0; p < NS; ++p) {
+        T a = ub[0];
+#pragma unroll
+        for (int m = 1; m < M; ++m) a = cmad(S::tab.phi_s[p][m], s.ch[0][m - 1], a);
+        const double u = static_cast<double>(a);
+        const double e = static_cast<double>(err[0]);
+        ok = ok && (u - e >= lo) && (u + e <= hi);
+        if constexpr (A0) {
+          const auto ax = P::aux(&a, I);
+#pragma unroll
+          for (int d = 0; d < D; ++d) a0[d] = fmax(a0[d], static_cast<double>(P::speed(&a, ax, d, I)));
+        }
+      }
+    }
+    return ok;
+  }
+
+  // Cheaper sufficient test without point evaluation: every Legendre product
+  // satisfies |phi_m| <= 1 on the cell, so u_v lies in [ubar_v - R_v, ubar_v
+  // + R_v] with R_v = sum_{m>=1} |c_vm| everywhere on K.  For Euler,
+  // rho e >= eps follows from E rho - |m|^2 / 2 >= eps rho, bounded below by
+  // (Ebar - R_E)(rhobar - R_rho) - sum_j (|mbar_j| + R_mj)^2 / 2 when both
+  // factors are positive.  A pass proves the limiter is the identity.
+  __device__ __forceinline__ static bool interval_pass(const State& s, const InstDev& I) {
+    double R[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      T r = T(0);
+#pragma unroll
+      for (int m = 0; m < MH; ++m) r += fabs(s.ch[v][m]);
+      // covers the rounding of the sum (at most MH terms)
+      R[v] = static_cast<double>(r) * (1.0 + (MH + 2) * (MIXED ? 0x1p-23 : 0x1p-52));
+    }
+    if constexpr (SYS == SYS_EULER) {
+      const double rlo = s.ub[0] - R[0];
+      const double elo = s.ub[D + 1] - R[D + 1];
+      if (!(rlo >= I.eps) || !(elo > 0.0)) return false;
+      double mm = 0.0;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const double mh = fabs(s.ub[1 + j]) + R[1 + j];
+        mm = fma(mh, mh, mm);
+      }
+      const double qlo = fma(elo, rlo, -0.5 * mm);
+      return qlo * (1.0 - 0x1p-40) >= I.eps * (s.ub[0] + R[0]);
+    } else {
+      return (s.ub[0] - R[0] >= I.blo) && (s.ub[0] + R[0] <= I.bhi);
+    }
+  }
+
+  // Scaling limiter on S_K, FP64 decisions.  Scalar: Prop. 2.4; Euler:
+  // density step then internal-energy step on the density-limited polynomial
+  // (Sec. 2.2.3).  A factor only acts where its bound is violated; it is
+  // clamped to [0, 1].
+  __device__ __forceinline__ static void limit_full(State& s, const InstDev& I) {
     double th_first = 1.0, th_rest = 1.0;
     if constexpr (SYS == SYS_EULER) {
       const double eps = I.eps;
@@ -463,7 +616,8 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
       bool low = false;
 #pragma unroll
       for (int p = 0; p < NS; ++p) {
-        const double rho = rb + th1 * (sk_var(s, p, 0) - rb);
+        const double r0 = sk_var(s, p, 0);
+        const double rho = (th1 == 1.0) ? r0 : rb + th1 * (r0 - rb);
         double ke = 0.0;
 #pragma unroll
         for (int j = 0; j < D; ++j) {
@@ -477,7 +631,8 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
       if (low) {
         double emin = INFINITY;
         for (int p = 0; p < NS; ++p) {
-          const double rho = rb + th1 * (sk_var(s, p, 0) - rb);
+          const double r0 = sk_var(s, p, 0);
+          const double rho = (th1 == 1.0) ? r0 : rb + th1 * (r0 - rb);
           double ke = 0.0;
           for (int j = 0; j < D; ++j) {
             const double mj = sk_var(s, p, 1 + j);
@@ -533,25 +688,43 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
     }
   }
 
-  // max over S_K of the wave speed per direction (FP64)
+  // limiter (when enabled) and, with A0, the wave-speed maxima of the result
+  template <bool A0>
+  __device__ __forceinline__ static void limit_and_speeds(State& s, const InstDev& I, double* a0) {
+    const bool pass = sk_pass<A0>(s, I, a0);
+    if (!pass && I.limiter) {
+      limit_full(s, I);
+      if constexpr (A0) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) a0[d] = 0.0;
+        sk_pass<true>(s, I, a0);
+      }
+    }
+  }
+
+  __device__ __forceinline__ static void limit(State& s, const InstDev& I) {
+    limit_and_speeds<false>(s, I, nullptr);
+  }
+
+  // max over S_K of the wave speed per direction
   __device__ __forceinline__ static void wave_speeds(const State& s, const InstDev& I, double* a0) {
 #pragma unroll
     for (int d = 0; d < D; ++d) a0[d] = 0.0;
-#pragma unroll
-    for (int p = 0; p < NS; ++p) {
-      double u[V];
-#pragma unroll
-      for (int v = 0; v < V; ++v) u[v] = sk_var(s, p, v);
-      const auto a = P::aux(u, I);
-#pragma unroll
-      for (int d = 0; d < D; ++d) a0[d] = fmax(a0[d], P::speed(u, a, d, I));
-    }
+    sk_pass<true>(s, I, a0);
   }
 };
 
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
+// Cells whose S_K test fails are written unlimited and queued; the queue
+// kernel below limits them right after the stage, at full lane occupancy
+// (they are a few percent of the cells but sit in many wavefronts).
+__device__ __forceinline__ void defer_cell(const KArgs& a, int inst, int64_t c) {
+  const unsigned idx = atomicAdd(a.qcount, 1u);
+  a.queue[idx] = make_int2(inst, static_cast<int>(c));
+}
+
 template <typename T>
 __device__ __forceinline__ T* hi_ptr(void* p, int64_t off) {
   return static_cast<T*>(p) + off;
@@ -580,9 +753,10 @@ __global__ __launch_bounds__(BLOCK) void k_stage_local(KArgs a) {
   T* o_hi = hi_ptr<T>(sel_hi(a.slots, sl_out), I.hi_off);
   const double dt = ctl->dt;
 
-  const int64_t c = bi.cell0 + threadIdx.x;
+  bool active;
+  const int64_t c = tile_cell(bi, D, I.n, I.ncell, active);
   bool bad = false, nonfin = false;
-  if (c < I.ncell) {
+  if (active) {
     typename C::State u;
     C::load(in_avg, in_hi, I.ncell, c, u);
     typename C::Acc r;
@@ -593,7 +767,8 @@ __global__ __launch_bounds__(BLOCK) void k_stage_local(KArgs a) {
     C::combine(base, r, out);
     bad = !C::average_ok(out, I);
     nonfin = !C::average_finite(out);
-    if (I.limiter) C::limit(out, I);
+    const bool pass = !I.limiter || C::interval_pass(out, I) || C::template sk_pass<false>(out, I, nullptr);
+    if (!pass) defer_cell(a, bi.inst, c);
     C::store(o_avg, o_hi, I.ncell, c, out);
   }
   raise_flag(&ctl->flags, bad, CRKDG_F_AVERAGE);
@@ -620,20 +795,19 @@ __global__ __launch_bounds__(BLOCK) void k_stage_final(KArgs a) {
   double* o_avg = sel_avg(a.slots, sl_out) + I.avg_off;
   T* o_hi = hi_ptr<T>(sel_hi(a.slots, sl_out), I.hi_off);
 
-  const int64_t c = bi.cell0 + threadIdx.x;
+  bool active;
+  const int64_t c = tile_cell(bi, D, I.n, I.ncell, active);
   bool bad = false, nonfin = false;
   double a0[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) a0[d] = 0.0;
-  if (c < I.ncell) {
+  if (active) {
     typename C::Acc r;
     C::zero(r);
-    typename C::State base;
-    C::load(b_avg, b_hi, I.ncell, c, base);
-    if (a.b[0] != 0.0) C::op_dg(base, b_avg, b_hi, c, I, dt * a.b[0], r);
-#pragma unroll
-    for (int j = 2; j <= 4; ++j) {
-      if (j > s || a.b[j - 1] == 0.0) continue;
+    // one inlined copy of F, applied to every stage with b_j != 0
+#pragma unroll 1
+    for (int j = 1; j <= s; ++j) {
+      if (a.b[j - 1] == 0.0) continue;
       const int sl = (cur + j - 1) % nsl;
       const double* j_avg = sel_avg(a.slots, sl) + I.avg_off;
       const T* j_hi = hi_ptr<T>(sel_hi(a.slots, sl), I.hi_off);
@@ -641,13 +815,27 @@ __global__ __launch_bounds__(BLOCK) void k_stage_final(KArgs a) {
       C::load(j_avg, j_hi, I.ncell, c, uj);
       C::op_dg(uj, j_avg, j_hi, c, I, dt * a.b[j - 1], r);
     }
+    typename C::State base;
+    C::load(b_avg, b_hi, I.ncell, c, base);
     typename C::State out;
     C::combine(base, r, out);
     bad = !C::average_ok(out, I);
     nonfin = !C::average_finite(out);
-    if (I.limiter) C::limit(out, I);
+    double sp[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) sp[d] = 0.0;
+    const bool pass = C::template sk_pass<true>(out, I, sp);
+    if (!pass && I.limiter) {
+      defer_cell(a, bi.inst, c);   // its speeds come from the limited state
+    } else {
+#pragma unroll
+      for (int d = 0; d < D; ++d) a0[d] = sp[d];
+    }
     C::store(o_avg, o_hi, I.ncell, c, out);
-    if (!bad && !nonfin) C::wave_speeds(out, I, a0);
+  }
+  if (bad || nonfin) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) a0[d] = 0.0;
   }
   raise_flag(&ctl->flags, bad, CRKDG_F_AVERAGE);
   raise_flag(&ctl->flags, nonfin, CRKDG_F_NONFINITE);
@@ -657,6 +845,41 @@ __global__ __launch_bounds__(BLOCK) void k_stage_final(KArgs a) {
     if ((threadIdx.x & 63) == 0 && m > 0.0)
       atomicMax(reinterpret_cast<unsigned long long*>(&ctl->a0_next[d]),
                 static_cast<unsigned long long>(__double_as_longlong(m)));
+  }
+}
+
+// Limiter of the cells a stage kernel queued (same slot rotation as the
+// stage); on the final stage also their wave speeds.
+template <int D, int K, int SP, int SYS, typename T, bool FINAL>
+__global__ __launch_bounds__(BLOCK) void k_limit_queue(KArgs a) {
+  using C = Cell<D, K, SP, SYS, T>;
+  const unsigned n = *a.qcount;
+  for (unsigned e = blockIdx.x * BLOCK + threadIdx.x; e < n; e += gridDim.x * BLOCK) {
+    const int2 it = a.queue[e];
+    const InstDev& I = a.inst[it.x];
+    crkdg_ctl* ctl = a.ctl + it.x;
+    const int s = I.stages;
+    const int cur = a.slots.rotate ? ctl->cur : 0;
+    const int sl_out = FINAL ? (cur + s) % (s + 1) : (cur + a.stage - 1) % (s + 1);
+    double* avg = sel_avg(a.slots, sl_out) + I.avg_off;
+    T* hi = hi_ptr<T>(sel_hi(a.slots, sl_out), I.hi_off);
+    typename C::State u;
+    C::load(avg, hi, I.ncell, it.y, u);
+    C::limit_full(u, I);
+    C::store(avg, hi, I.ncell, it.y, u);
+    if constexpr (FINAL) {
+      double a0[D];
+      C::wave_speeds(u, I, a0);
+      // the stage kernel already holds the maximum of the other cells: only
+      // a larger speed needs the (contended) atomic; a stale read only costs
+      // an unneeded atomic, never a lost update, as the value only grows
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        const unsigned long long bits = static_cast<unsigned long long>(__double_as_longlong(a0[d]));
+        unsigned long long* dst = reinterpret_cast<unsigned long long*>(&ctl->a0_next[d]);
+        if (bits > __atomic_load_n(dst, __ATOMIC_RELAXED)) atomicMax(dst, bits);
+      }
+    }
   }
 }
 
@@ -670,9 +893,10 @@ __global__ __launch_bounds__(BLOCK) void k_limit(KArgs a) {
   crkdg_ctl* ctl = a.ctl ? a.ctl + bi.inst : nullptr;
   double* avg = a.slots.avg[0] + I.avg_off;
   T* hi = hi_ptr<T>(a.slots.hi[0], I.hi_off);
-  const int64_t c = bi.cell0 + threadIdx.x;
+  bool active;
+  const int64_t c = tile_cell(bi, D, I.n, I.ncell, active);
   bool bad = false;
-  if (c < I.ncell) {
+  if (active) {
     typename C::State u;
     C::load(avg, hi, I.ncell, c, u);
     bad = !C::average_ok(u, I);
@@ -695,11 +919,12 @@ __global__ __launch_bounds__(BLOCK) void k_cfl(KArgs a) {
   const int cur = a.slots.rotate ? ctl->cur : 0;
   const double* avg = sel_avg(a.slots, cur) + I.avg_off;
   const T* hi = hi_ptr<T>(sel_hi(a.slots, cur), I.hi_off);
-  const int64_t c = bi.cell0 + threadIdx.x;
+  bool active;
+  const int64_t c = tile_cell(bi, D, I.n, I.ncell, active);
   double a0[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) a0[d] = 0.0;
-  if (c < I.ncell) {
+  if (active) {
     typename C::State u;
     C::load(avg, hi, I.ncell, c, u);
     C::wave_speeds(u, I, a0);
@@ -724,8 +949,9 @@ __global__ __launch_bounds__(BLOCK) void k_project(KArgs a) {
   double* avg = a.slots.avg[0] + I.avg_off;
   T* hi = hi_ptr<T>(a.slots.hi[0], I.hi_off);
   const double* smp = a.samples + I.avg_off * S::NQ;
-  const int64_t c = bi.cell0 + threadIdx.x;
-  if (c >= I.ncell) return;
+  bool active;
+  const int64_t c = tile_cell(bi, D, I.n, I.ncell, active);
+  if (!active) return;
   typename C::State u;
 #pragma unroll
   for (int v = 0; v < C::V; ++v) {

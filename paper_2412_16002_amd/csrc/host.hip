@@ -76,7 +76,11 @@ struct Group {
   std::vector<int> insts;
   int nblocks = 0;              // grid size (a multiple of 8, padded)
   BlockItem* d_bmap = nullptr;
+  int64_t ncells = 0;           // cells of all instances of the group
+  int64_t queue_off = 0;        // first entry of the group's deferred-limiter queue
 };
+
+constexpr int QSTAGES = 8;      // counters per group, indexed by stage number
 
 }  // namespace
 
@@ -88,6 +92,8 @@ struct crkdg_mesh {
   std::vector<Group> groups;
   InstDev* d_inst = nullptr;
   double* d_partial = nullptr;  // [total logical blocks][5]
+  int2* d_queue = nullptr;      // deferred-limiter queue, one region per group
+  unsigned* d_qcount = nullptr; // [groups][QSTAGES] queue lengths
   int total_lblocks = 0;
   int max_stages = 0;
   int device = 0;
@@ -103,7 +109,10 @@ std::vector<BlockItem> xcd_block_map(const std::vector<BlockItem>& logical) {
   const int nl = static_cast<int>(logical.size());
   const int nx = 8;
   const int chunk = (nl + nx - 1) / nx;
-  std::vector<BlockItem> phys(static_cast<size_t>(chunk) * nx, BlockItem{-1, -1, 0});
+  BlockItem pad{};
+  pad.inst = -1;
+  pad.lblock = -1;
+  std::vector<BlockItem> phys(static_cast<size_t>(chunk) * nx, pad);
   for (int b = 0; b < chunk * nx; ++b) {
     const int x = b % nx, j = b / nx;
     const int l = x * chunk + j;
@@ -134,12 +143,19 @@ int validate(const crkdg_problem& p, int idx) {
   if (p.max_halvings < 0) return bad("max_halvings must be >= 0");
   int64_t nc = 1;
   for (int d = 0; d < p.dim; ++d) nc *= p.n[d];
-  if (nc > (int64_t(1) << 40)) return bad("too many cells");
+  if (nc > INT32_MAX) return bad("more than 2^31 - 1 cells in one instance");
   return CRKDG_OK;
 }
 
-__global__ void k_controller(crkdg_ctl* ctl, const InstDev* inst, int n) {
+__global__ void k_zero_u32(unsigned* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+__global__ void k_controller(crkdg_ctl* ctl, const InstDev* inst, int n, unsigned* qcount, int nq) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  // the deferred-limiter queues of this attempt have been drained
+  for (int k = i; k < nq; k += gridDim.x * blockDim.x) qcount[k] = 0u;
   if (i >= n) return;
   crkdg_ctl& c = ctl[i];
   const InstDev& I = inst[i];
@@ -212,9 +228,10 @@ __global__ __launch_bounds__(BLOCK) void k_totals_partial(const InstDev* inst, c
   if (bi.inst < 0) return;
   const InstDev& I = inst[bi.inst];
   __shared__ double sh[BLOCK];
-  const int64_t c = bi.cell0 + threadIdx.x;
+  bool active;
+  const int64_t c = tile_cell(bi, I.dim, I.n, I.ncell, active);
   for (int v = 0; v < V; ++v) {
-    sh[threadIdx.x] = (c < I.ncell) ? I.vol * avg[I.avg_off + v * I.ncell + c] : 0.0;
+    sh[threadIdx.x] = active ? I.vol * avg[I.avg_off + v * I.ncell + c] : 0.0;
     __syncthreads();
     for (int s = BLOCK / 2; s > 0; s >>= 1) {
       if (static_cast<int>(threadIdx.x) < s) sh[threadIdx.x] += sh[threadIdx.x + s];
@@ -343,6 +360,7 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
       }
     }
     I.vol = vol;
+    I.dim = p.dim;
     I.stages = p.stages;
     I.limiter = p.limiter;
     I.max_halvings = p.max_halvings;
@@ -368,15 +386,27 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
       g = it->second;
     }
     m->groups[g].insts.push_back(i);
-    const int64_t nb = (nc + BLOCK - 1) / BLOCK;
+    const int64_t tx = (p.dim == 1) ? (nc + BLOCK - 1) / BLOCK : (p.n[0] + TILE_X - 1) / TILE_X;
+    const int64_t ty = (p.dim == 1) ? 1 : (p.n[1] + TILE_Y - 1) / TILE_Y;
+    const int64_t tz = (p.dim == 3) ? p.n[2] : 1;
+    const int64_t nb = tx * ty * tz;
     if (nb + lblock > (int64_t(1) << 30)) {
       delete m;
       return fail(CRKDG_E_ARG, "too many cells in total");
     }
     I.first_block = lblock;
     I.n_blocks = static_cast<int>(nb);
-    for (int64_t b = 0; b < nb; ++b) logical[g].push_back(BlockItem{i, lblock + static_cast<int>(b), b * BLOCK});
-    lblock += static_cast<int>(nb);
+    for (int64_t z = 0; z < tz; ++z)
+      for (int64_t y = 0; y < ty; ++y)
+        for (int64_t x = 0; x < tx; ++x) {
+          BlockItem it{};
+          it.inst = i;
+          it.lblock = lblock++;
+          it.x0 = static_cast<int32_t>(p.dim == 1 ? x * BLOCK : x * TILE_X);
+          it.y0 = static_cast<int32_t>(y * TILE_Y);
+          it.z = static_cast<int32_t>(z);
+          logical[g].push_back(it);
+        }
   }
   m->total_lblocks = lblock;
 
@@ -399,6 +429,19 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
       return cleanup("hipMemcpy", e);
   }
 
+  int64_t qtotal = 0;
+  for (Group& G : m->groups) {
+    G.ncells = 0;
+    for (int i : G.insts) G.ncells += m->lay[i].n_cells;
+    G.queue_off = qtotal;
+    qtotal += G.ncells;
+  }
+  if ((e = hipMalloc(&m->d_queue, sizeof(int2) * std::max<int64_t>(1, qtotal))) != hipSuccess)
+    return cleanup("hipMalloc", e);
+  const int nq = static_cast<int>(m->groups.size()) * QSTAGES;
+  if ((e = hipMalloc(&m->d_qcount, sizeof(unsigned) * nq)) != hipSuccess) return cleanup("hipMalloc", e);
+  if ((e = hipMemset(m->d_qcount, 0, sizeof(unsigned) * nq)) != hipSuccess) return cleanup("hipMemset", e);
+
   crkdg_layout& lo = m->layout;
   lo.n_inst = n_inst;
   lo.hi_bytes = (prec == CRKDG_FP64) ? 8 : 4;
@@ -418,6 +461,8 @@ int crkdg_free_mesh(crkdg_mesh* m) {
     if (g.d_bmap) hipFree(g.d_bmap);
   if (m->d_inst) hipFree(m->d_inst);
   if (m->d_partial) hipFree(m->d_partial);
+  if (m->d_queue) hipFree(m->d_queue);
+  if (m->d_qcount) hipFree(m->d_qcount);
   delete m;
   return CRKDG_OK;
 }
@@ -594,21 +639,29 @@ int crkdg_start(crkdg_mesh* m, const crkdg_state* slots, int32_t cur, crkdg_ctl*
   }
   HIP_TRY(hipMemcpyAsync(d_ctl, h.data(), sizeof(crkdg_ctl) * n, hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
+  const int nq = static_cast<int>(m->groups.size()) * QSTAGES;
+  hipLaunchKernelGGL(k_zero_u32, dim3((nq + 63) / 64), dim3(64), 0, s, m->d_qcount, nq);
   return launch_cfl(m, slots, ns, 1, d_ctl, s);
 }
 
-static int launch_stage(crkdg_mesh* m, const Group& g, int stage, const Slots& slots, crkdg_ctl* d_ctl,
+static int launch_stage(crkdg_mesh* m, int gi, int stage, const Slots& slots, crkdg_ctl* d_ctl,
                         hipStream_t s) {
+  const Group& g = m->groups[gi];
   const Butcher bt = butcher(g.stages);
   KArgs a = base_args(m, g, d_ctl);
   a.slots = slots;
   a.stage = stage;
+  a.queue = m->d_queue + g.queue_off;
+  a.qcount = m->d_qcount + gi * QSTAGES + stage;
+  const int qblocks = static_cast<int>(std::min<int64_t>(1024, (g.ncells + BLOCK - 1) / BLOCK));
   if (stage <= g.stages) {
     a.a = bt.a[stage];
     g.ops->stage_local(a, g.nblocks, s);
+    g.ops->queue_local(a, qblocks, s);
   } else {
     for (int j = 0; j < 4; ++j) a.b[j] = bt.b[j];
     g.ops->stage_final(a, g.nblocks, s);
+    g.ops->queue_final(a, qblocks, s);
   }
   return CRKDG_OK;
 }
@@ -621,8 +674,12 @@ int crkdg_stage(crkdg_mesh* m, int32_t stage, const crkdg_state* states, int32_t
   if (int rc = set_device(m)) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   bool any = false;
-  for (const Group& g : m->groups) {
-    if (stage < 2 || stage > g.stages + 1) continue;
+  if (stage < 2 || stage >= QSTAGES) return fail(CRKDG_E_ARG, "stage index out of range");
+  const int nq = static_cast<int>(m->groups.size()) * QSTAGES;
+  hipLaunchKernelGGL(k_zero_u32, dim3((nq + 63) / 64), dim3(64), 0, s, m->d_qcount, nq);
+  for (int gi = 0; gi < static_cast<int>(m->groups.size()); ++gi) {
+    const Group& g = m->groups[gi];
+    if (stage > g.stages + 1) continue;
     // stage 2..s reads u~^(stage-1); the final stage reads u~^(j), b_j != 0
     const int need = (stage <= g.stages) ? stage - 1 : g.stages;
     if (n_states < need) return fail(CRKDG_E_ARG, "too few states for this stage");
@@ -639,7 +696,7 @@ int crkdg_stage(crkdg_mesh* m, int32_t stage, const crkdg_state* states, int32_t
     sl.hi[oslot] = out.hi;
     sl.n = g.stages + 1;
     sl.rotate = 0;
-    launch_stage(m, g, stage, sl, d_ctl, s);
+    launch_stage(m, gi, stage, sl, d_ctl, s);
     any = true;
   }
   if (!any) return fail(CRKDG_E_ARG, "stage index out of range for every instance");
@@ -649,10 +706,12 @@ int crkdg_stage(crkdg_mesh* m, int32_t stage, const crkdg_state* states, int32_t
 
 static int enqueue_attempt(crkdg_mesh* m, const Slots& sl, crkdg_ctl* d_ctl, hipStream_t s) {
   for (int stage = 2; stage <= m->max_stages + 1; ++stage)
-    for (const Group& g : m->groups)
-      if (stage <= g.stages + 1) launch_stage(m, g, stage, sl, d_ctl, s);
+    for (int gi = 0; gi < static_cast<int>(m->groups.size()); ++gi)
+      if (stage <= m->groups[gi].stages + 1) launch_stage(m, gi, stage, sl, d_ctl, s);
   const int n = m->layout.n_inst;
-  hipLaunchKernelGGL(k_controller, dim3((n + 63) / 64), dim3(64), 0, s, d_ctl, m->d_inst, n);
+  const int nq = static_cast<int>(m->groups.size()) * QSTAGES;
+  hipLaunchKernelGGL(k_controller, dim3((std::max(n, nq) + 63) / 64), dim3(64), 0, s, d_ctl, m->d_inst, n,
+                     m->d_qcount, nq);
   HIP_TRY(hipGetLastError());
   return CRKDG_OK;
 }

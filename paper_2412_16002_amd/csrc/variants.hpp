@@ -11,7 +11,7 @@ using Launch = void (*)(const KArgs&, int nblocks, hipStream_t);
 struct VariantOps {
   int dim, k, space, system, precision;
   int M, V, NQ, NS;
-  Launch stage_local, stage_final, limit, cfl, project;
+  Launch stage_local, stage_final, limit, cfl, project, queue_local, queue_final;
 };
 
 template <int D, int K, int SP, int SYS, typename T> struct Ops {
@@ -31,10 +31,16 @@ template <int D, int K, int SP, int SYS, typename T> struct Ops {
   static void project(const KArgs& a, int nb, hipStream_t s) {
     hipLaunchKernelGGL((k_project<D, K, SP, SYS, T>), dim3(nb), dim3(BLOCK), 0, s, a);
   }
+  static void queue_local(const KArgs& a, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((k_limit_queue<D, K, SP, SYS, T, false>), dim3(nb), dim3(BLOCK), 0, s, a);
+  }
+  static void queue_final(const KArgs& a, int nb, hipStream_t s) {
+    hipLaunchKernelGGL((k_limit_queue<D, K, SP, SYS, T, true>), dim3(nb), dim3(BLOCK), 0, s, a);
+  }
   static VariantOps make() {
     return VariantOps{D, K, SP, SYS, sizeof(T) == 8 ? CRKDG_FP64 : CRKDG_MIXED,
                       C::M, C::V, C::S::NQ, C::NS,
-                      &stage_local, &stage_final, &limit, &cfl, &project};
+                      &stage_local, &stage_final, &limit, &cfl, &project, &queue_local, &queue_final};
   }
 };
 

@@ -10,10 +10,6 @@ import numpy as np
 import oracle
 from paper_2412_16002_amd import inputs
 
-SYS = {"advection": 0, "burgers": 1, "euler": 2}
-BC = {"periodic": 0, "outflow": 1}
-
-
 def oracle_problem(params: dict) -> oracle.Problem:
     d = params["dim"]
     bc = tuple(params.get("bc", ("periodic",) * d)) + ("periodic",) * (3 - d)
@@ -29,18 +25,7 @@ def oracle_problem(params: dict) -> oracle.Problem:
 
 def gpu_problem(params: dict):
     from paper_2412_16002_amd import crkdg
-    d = params["dim"]
-    bc = tuple(BC[b] for b in params.get("bc", ("periodic",) * d)) + (0,) * (3 - d)
-    n = tuple(params["n"]) + (1,) * (3 - d)
-    return crkdg.Problem(
-        dim=d, n=n, system=SYS[params["system"]], k=params["k"],
-        space=0 if params.get("space", "Q") == "Q" else 1, stages=params["stages"],
-        precision=0 if params.get("precision", "fp64") == "fp64" else 1,
-        lo=tuple(params.get("lo", (0.0, 0.0, 0.0))), hi=tuple(params.get("hi", (1.0, 1.0, 1.0))),
-        bc=bc, vel=tuple(params.get("vel", (1.0, 1.0, 1.0))), gamma=params.get("gamma", 1.4),
-        bound_lo=params.get("bound_lo", -math.inf), bound_hi=params.get("bound_hi", math.inf),
-        eps=params.get("eps", 1e-8), limiter=int(params.get("limiter", True)),
-        cfl=params.get("cfl", 0.1), max_halvings=params.get("max_halvings", 40))
+    return crkdg.problem_from_params(params)
 
 
 def mode_degrees(o: oracle.CRKDG):
