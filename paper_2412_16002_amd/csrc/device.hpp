@@ -90,8 +90,9 @@ struct KArgs {
   double b[4];         // b_1..b_s (final stage)
   const double* samples;
   double* out;         // totals partials / other outputs
-  int2* queue;         // cells whose limiter is deferred (instance, cell)
+  void* queue;         // records of the cells whose limiter is deferred
   unsigned* qcount;    // number of queued cells of this stage
+  unsigned qcap;       // record capacity of the queue (cells of the group)
 };
 
 // ---------------------------------------------------------------------------
@@ -706,6 +707,33 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
     limit_and_speeds<false>(s, I, nullptr);
   }
 
+  // Cells whose S_K test fails are not limited in the stage kernel: their
+  // unlimited state goes, as one contiguous record, into a queue that a
+  // small kernel drains right after the stage (the FP64 limiter then runs
+  // at full lane occupancy instead of stalling the wavefronts that contain
+  // such a cell; they are a few percent of the cells, near discontinuities).
+  struct Record {
+    int32_t inst;
+    int32_t cell;
+    double ub[V];
+    T ch[V][MH];
+  };
+  // the queue holds a record for every cell of the group, so it never
+  // overflows; the bound check only guards memory against a stale counter
+  __device__ __forceinline__ static void enqueue(const KArgs& a, int inst, int64_t c, const State& s) {
+    const unsigned idx = atomicAdd(a.qcount, 1u);
+    if (idx >= a.qcap) return;
+    Record* r = static_cast<Record*>(a.queue) + idx;
+    r->inst = inst;
+    r->cell = static_cast<int32_t>(c);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      r->ub[v] = s.ub[v];
+#pragma unroll
+      for (int m = 0; m < MH; ++m) r->ch[v][m] = s.ch[v][m];
+    }
+  }
+
   // max over S_K of the wave speed per direction
   __device__ __forceinline__ static void wave_speeds(const State& s, const InstDev& I, double* a0) {
 #pragma unroll
@@ -717,14 +745,6 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
-// Cells whose S_K test fails are written unlimited and queued; the queue
-// kernel below limits them right after the stage, at full lane occupancy
-// (they are a few percent of the cells but sit in many wavefronts).
-__device__ __forceinline__ void defer_cell(const KArgs& a, int inst, int64_t c) {
-  const unsigned idx = atomicAdd(a.qcount, 1u);
-  a.queue[idx] = make_int2(inst, static_cast<int>(c));
-}
-
 template <typename T>
 __device__ __forceinline__ T* hi_ptr(void* p, int64_t off) {
   return static_cast<T*>(p) + off;
@@ -768,8 +788,8 @@ __global__ __launch_bounds__(BLOCK) void k_stage_local(KArgs a) {
     bad = !C::average_ok(out, I);
     nonfin = !C::average_finite(out);
     const bool pass = !I.limiter || C::interval_pass(out, I) || C::template sk_pass<false>(out, I, nullptr);
-    if (!pass) defer_cell(a, bi.inst, c);
-    C::store(o_avg, o_hi, I.ncell, c, out);
+    if (pass) C::store(o_avg, o_hi, I.ncell, c, out);
+    else C::enqueue(a, bi.inst, c, out);
   }
   raise_flag(&ctl->flags, bad, CRKDG_F_AVERAGE);
   raise_flag(&ctl->flags, nonfin, CRKDG_F_NONFINITE);
@@ -826,12 +846,13 @@ __global__ __launch_bounds__(BLOCK) void k_stage_final(KArgs a) {
     for (int d = 0; d < D; ++d) sp[d] = 0.0;
     const bool pass = C::template sk_pass<true>(out, I, sp);
     if (!pass && I.limiter) {
-      defer_cell(a, bi.inst, c);   // its speeds come from the limited state
+      // limited (and its speeds taken) by the queue kernel
+      C::enqueue(a, bi.inst, c, out);
     } else {
 #pragma unroll
       for (int d = 0; d < D; ++d) a0[d] = sp[d];
+      C::store(o_avg, o_hi, I.ncell, c, out);
     }
-    C::store(o_avg, o_hi, I.ncell, c, out);
   }
   if (bad || nonfin) {
 #pragma unroll
@@ -853,20 +874,27 @@ __global__ __launch_bounds__(BLOCK) void k_stage_final(KArgs a) {
 template <int D, int K, int SP, int SYS, typename T, bool FINAL>
 __global__ __launch_bounds__(BLOCK) void k_limit_queue(KArgs a) {
   using C = Cell<D, K, SP, SYS, T>;
-  const unsigned n = *a.qcount;
+  const unsigned n0 = *a.qcount;
+  const unsigned n = n0 < a.qcap ? n0 : a.qcap;
+  const typename C::Record* rec = static_cast<const typename C::Record*>(a.queue);
   for (unsigned e = blockIdx.x * BLOCK + threadIdx.x; e < n; e += gridDim.x * BLOCK) {
-    const int2 it = a.queue[e];
-    const InstDev& I = a.inst[it.x];
-    crkdg_ctl* ctl = a.ctl + it.x;
+    const typename C::Record& r = rec[e];
+    const InstDev& I = a.inst[r.inst];
+    crkdg_ctl* ctl = a.ctl + r.inst;
     const int s = I.stages;
     const int cur = a.slots.rotate ? ctl->cur : 0;
     const int sl_out = FINAL ? (cur + s) % (s + 1) : (cur + a.stage - 1) % (s + 1);
     double* avg = sel_avg(a.slots, sl_out) + I.avg_off;
     T* hi = hi_ptr<T>(sel_hi(a.slots, sl_out), I.hi_off);
     typename C::State u;
-    C::load(avg, hi, I.ncell, it.y, u);
+#pragma unroll
+    for (int v = 0; v < C::V; ++v) {
+      u.ub[v] = r.ub[v];
+#pragma unroll
+      for (int m = 0; m < C::MH; ++m) u.ch[v][m] = r.ch[v][m];
+    }
     C::limit_full(u, I);
-    C::store(avg, hi, I.ncell, it.y, u);
+    C::store(avg, hi, I.ncell, r.cell, u);
     if constexpr (FINAL) {
       double a0[D];
       C::wave_speeds(u, I, a0);

@@ -77,10 +77,11 @@ struct Group {
   int nblocks = 0;              // grid size (a multiple of 8, padded)
   BlockItem* d_bmap = nullptr;
   int64_t ncells = 0;           // cells of all instances of the group
-  int64_t queue_off = 0;        // first entry of the group's deferred-limiter queue
+  int64_t queue_off = 0;        // byte offset of the group's deferred-limiter queue
+  unsigned qcap = 0;            // its record capacity
 };
 
-constexpr int QSTAGES = 8;      // counters per group, indexed by stage number
+constexpr int QSTAGES = 8;      // queue counters per group, indexed by stage number
 
 }  // namespace
 
@@ -92,8 +93,8 @@ struct crkdg_mesh {
   std::vector<Group> groups;
   InstDev* d_inst = nullptr;
   double* d_partial = nullptr;  // [total logical blocks][5]
-  int2* d_queue = nullptr;      // deferred-limiter queue, one region per group
-  unsigned* d_qcount = nullptr; // [groups][QSTAGES] queue lengths
+  char* d_queue = nullptr;      // deferred-limiter queue records, one region per group
+  unsigned* d_qcount = nullptr; // [groups][QSTAGES] deferred-limiter queue lengths
   int total_lblocks = 0;
   int max_stages = 0;
   int device = 0;
@@ -154,7 +155,7 @@ __global__ void k_zero_u32(unsigned* p, int n) {
 
 __global__ void k_controller(crkdg_ctl* ctl, const InstDev* inst, int n, unsigned* qcount, int nq) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  // the deferred-limiter queues of this attempt have been drained
+  // every deferred-limiter queue of this attempt has been drained
   for (int k = i; k < nq; k += gridDim.x * blockDim.x) qcount[k] = 0u;
   if (i >= n) return;
   crkdg_ctl& c = ctl[i];
@@ -429,14 +430,22 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
       return cleanup("hipMemcpy", e);
   }
 
+  // deferred-limiter queue: one record per cell of the group, so a stage
+  // can queue every cell (allocated once, with the mesh)
   int64_t qtotal = 0;
   for (Group& G : m->groups) {
     G.ncells = 0;
     for (int i : G.insts) G.ncells += m->lay[i].n_cells;
+    if (G.ncells > UINT32_MAX) {
+      crkdg_free_mesh(m);
+      return fail(CRKDG_E_ARG, "more than 2^32 - 1 cells share one kernel variant");
+    }
+    G.qcap = static_cast<unsigned>(G.ncells);
     G.queue_off = qtotal;
-    qtotal += G.ncells;
+    qtotal += static_cast<int64_t>(G.qcap) * G.ops->rec_bytes;
+    qtotal = (qtotal + 255) / 256 * 256;
   }
-  if ((e = hipMalloc(&m->d_queue, sizeof(int2) * std::max<int64_t>(1, qtotal))) != hipSuccess)
+  if ((e = hipMalloc(&m->d_queue, std::max<int64_t>(256, qtotal))) != hipSuccess)
     return cleanup("hipMalloc", e);
   const int nq = static_cast<int>(m->groups.size()) * QSTAGES;
   if ((e = hipMalloc(&m->d_qcount, sizeof(unsigned) * nq)) != hipSuccess) return cleanup("hipMalloc", e);
@@ -647,13 +656,19 @@ int crkdg_start(crkdg_mesh* m, const crkdg_state* slots, int32_t cur, crkdg_ctl*
 static int launch_stage(crkdg_mesh* m, int gi, int stage, const Slots& slots, crkdg_ctl* d_ctl,
                         hipStream_t s) {
   const Group& g = m->groups[gi];
+  if (stage < 2 || stage >= QSTAGES || stage > g.stages + 1)
+    return fail(CRKDG_E_ARG, "stage index out of range");
   const Butcher bt = butcher(g.stages);
   KArgs a = base_args(m, g, d_ctl);
   a.slots = slots;
   a.stage = stage;
   a.queue = m->d_queue + g.queue_off;
+  a.qcap = g.qcap;
   a.qcount = m->d_qcount + gi * QSTAGES + stage;
-  const int qblocks = static_cast<int>(std::min<int64_t>(1024, (g.ncells + BLOCK - 1) / BLOCK));
+  // every counter is cleared by the controller at the end of an attempt
+  // (crkdg_stage clears its own after the stage)
+  // the queue holds a few percent of the cells: up to 256 workgroups drain it
+  const int qblocks = static_cast<int>(std::min<int64_t>(256, (g.ncells + BLOCK - 1) / BLOCK));
   if (stage <= g.stages) {
     a.a = bt.a[stage];
     g.ops->stage_local(a, g.nblocks, s);
@@ -675,8 +690,6 @@ int crkdg_stage(crkdg_mesh* m, int32_t stage, const crkdg_state* states, int32_t
   hipStream_t s = static_cast<hipStream_t>(stream);
   bool any = false;
   if (stage < 2 || stage >= QSTAGES) return fail(CRKDG_E_ARG, "stage index out of range");
-  const int nq = static_cast<int>(m->groups.size()) * QSTAGES;
-  hipLaunchKernelGGL(k_zero_u32, dim3((nq + 63) / 64), dim3(64), 0, s, m->d_qcount, nq);
   for (int gi = 0; gi < static_cast<int>(m->groups.size()); ++gi) {
     const Group& g = m->groups[gi];
     if (stage > g.stages + 1) continue;
@@ -696,7 +709,8 @@ int crkdg_stage(crkdg_mesh* m, int32_t stage, const crkdg_state* states, int32_t
     sl.hi[oslot] = out.hi;
     sl.n = g.stages + 1;
     sl.rotate = 0;
-    launch_stage(m, gi, stage, sl, d_ctl, s);
+    if (int rc = launch_stage(m, gi, stage, sl, d_ctl, s)) return rc;
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, m->d_qcount + gi * QSTAGES + stage, 1);
     any = true;
   }
   if (!any) return fail(CRKDG_E_ARG, "stage index out of range for every instance");
@@ -707,7 +721,8 @@ int crkdg_stage(crkdg_mesh* m, int32_t stage, const crkdg_state* states, int32_t
 static int enqueue_attempt(crkdg_mesh* m, const Slots& sl, crkdg_ctl* d_ctl, hipStream_t s) {
   for (int stage = 2; stage <= m->max_stages + 1; ++stage)
     for (int gi = 0; gi < static_cast<int>(m->groups.size()); ++gi)
-      if (stage <= m->groups[gi].stages + 1) launch_stage(m, gi, stage, sl, d_ctl, s);
+      if (stage <= m->groups[gi].stages + 1)
+        if (int rc = launch_stage(m, gi, stage, sl, d_ctl, s)) return rc;
   const int n = m->layout.n_inst;
   const int nq = static_cast<int>(m->groups.size()) * QSTAGES;
   hipLaunchKernelGGL(k_controller, dim3((std::max(n, nq) + 63) / 64), dim3(64), 0, s, d_ctl, m->d_inst, n,

@@ -11,6 +11,7 @@ using Launch = void (*)(const KArgs&, int nblocks, hipStream_t);
 struct VariantOps {
   int dim, k, space, system, precision;
   int M, V, NQ, NS;
+  int rec_bytes;   // bytes of one deferred-limiter queue record
   Launch stage_local, stage_final, limit, cfl, project, queue_local, queue_final;
 };
 
@@ -39,7 +40,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Ops {
   }
   static VariantOps make() {
     return VariantOps{D, K, SP, SYS, sizeof(T) == 8 ? CRKDG_FP64 : CRKDG_MIXED,
-                      C::M, C::V, C::S::NQ, C::NS,
+                      C::M, C::V, C::S::NQ, C::NS, static_cast<int>(sizeof(typename C::Record)),
                       &stage_local, &stage_final, &limit, &cfl, &project, &queue_local, &queue_final};
   }
 };
