@@ -166,8 +166,13 @@ template <int D, int SYS> struct Phys {
     T p;       // pressure
   };
 
+  // The flux, the auxiliary quantities and the wave speed are evaluated by
+  // both cells of a face on the same trace values; floating-point
+  // contraction is switched off here (explicit fma only) so that both
+  // evaluations are bitwise identical whatever code they are inlined into.
   template <typename T>
   __device__ __forceinline__ static Aux<T> aux(const T* u, const InstDev& I) {
+#pragma clang fp contract(off)
     Aux<T> a{};
     if constexpr (SYS == SYS_EULER) {
       a.ir = recip(u[0]);
@@ -185,6 +190,7 @@ template <int D, int SYS> struct Phys {
   template <typename T>
   __device__ __forceinline__ static void flux(const T* u, const Aux<T>& a, int d, const InstDev& I,
                                               T* f) {
+#pragma clang fp contract(off)
     if constexpr (SYS == SYS_ADV) {
       f[0] = T(I.vel[d]) * u[0];
     } else if constexpr (SYS == SYS_BURG) {
@@ -200,6 +206,7 @@ template <int D, int SYS> struct Phys {
   // largest |eigenvalue| of df_d/du
   template <typename T>
   __device__ __forceinline__ static T speed(const T* u, const Aux<T>& a, int d, const InstDev& I) {
+#pragma clang fp contract(off)
     if constexpr (SYS == SYS_ADV) {
       return T(fabs(I.vel[d]));
     } else if constexpr (SYS == SYS_BURG) {
@@ -406,13 +413,18 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
         alpha = fmax(alpha, fmax(P::speed(uL, aL, d, I), P::speed(uR, aR, d, I)));
       }
       T fn[S::NFP][V];
+      {
+        // same operations, in the same order, in both cells of the face
+#pragma clang fp contract(off)
+        const T ha = T(0.5) * alpha;
 #pragma unroll
-      for (int b = 0; b < S::NFP; ++b) {
-        const T* uL = upper ? ui[b] : ue[b];
-        const T* uR = upper ? ue[b] : ui[b];
+        for (int b = 0; b < S::NFP; ++b) {
+          const T* uL = upper ? ui[b] : ue[b];
+          const T* uR = upper ? ue[b] : ui[b];
 #pragma unroll
-        for (int v = 0; v < V; ++v)
-          fn[b][v] = T(0.5) * (fL[b][v] + fR[b][v]) - T(0.5) * alpha * (uR[v] - uL[v]);
+          for (int v = 0; v < V; ++v)
+            fn[b][v] = fma(-ha, uR[v] - uL[v], T(0.5) * (fL[b][v] + fR[b][v]));
+        }
       }
       face_accum(f, fn, I, scale, r);
     }
