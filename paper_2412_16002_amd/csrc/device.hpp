@@ -218,6 +218,47 @@ template <int D, int SYS> struct Phys {
 };
 
 // ---------------------------------------------------------------------------
+// Basis tables in the arithmetic type, for the spaces whose point loops stay
+// rolled (see Cell::BIG): a row is picked by a loop counter that is uniform
+// across the wavefront, so it arrives through scalar loads.
+// ---------------------------------------------------------------------------
+template <int D, int K, int SP, typename T> struct RtTab {
+  using S = Space<D, K, SP>;
+  static constexpr int TM = ipow(K + 1, D - 1);  // tangential modes of a face
+  T phi_v[S::NQ][S::M];
+  T cvol[S::NQ][S::M][D];
+  T phi_s[S::NS_RAW][S::M];
+  T ftan[S::NFP][TM];    // tangential Legendre products at the face points
+  T wftan[S::NFP][TM];   // the same times the face weight
+  constexpr RtTab() : phi_v{}, cvol{}, phi_s{}, ftan{}, wftan{} {
+    for (int q = 0; q < S::NQ; ++q)
+      for (int m = 0; m < S::M; ++m) {
+        phi_v[q][m] = static_cast<T>(S::tab.phi_v[q][m]);
+        for (int d = 0; d < D; ++d) cvol[q][m][d] = static_cast<T>(S::tab.cvol[q][m][d]);
+      }
+    for (int p = 0; p < S::NS; ++p)
+      for (int m = 0; m < S::M; ++m) phi_s[p][m] = static_cast<T>(S::tab.phi_s[p][m]);
+    // face point b: tangential Gauss indices, lower direction fastest (as in
+    // Space::Tables); tangential mode t likewise
+    for (int b = 0; b < S::NFP; ++b)
+      for (int t = 0; t < TM; ++t) {
+        double v = 1.0;
+        int rb = b, rt = t;
+        for (int j = 0; j < D - 1; ++j) {
+          v *= leg(rt % (K + 1), S::gx(rb % S::NG));
+          rb /= S::NG;
+          rt /= (K + 1);
+        }
+        ftan[b][t] = static_cast<T>(v);
+        wftan[b][t] = static_cast<T>(S::tab.wb[b] * v);
+      }
+  }
+};
+template <int D, int K, int SP, typename T> struct Rt {
+  static constexpr RtTab<D, K, SP, T> tab{};
+};
+
+// ---------------------------------------------------------------------------
 // the cell kernels of one variant
 // ---------------------------------------------------------------------------
 template <int D, int K, int SP, int SYS, typename T> struct Cell {
@@ -228,6 +269,17 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
   static constexpr int MH = M - 1;
   static constexpr int NS = S::NS;
   static constexpr bool MIXED = sizeof(T) == 4;
+
+  // Large spaces (3D Q^2 Euler: 27 modes x 5 variables) keep their point
+  // loops rolled.  The work of one point is still unrolled over modes and
+  // variables, with table rows from Rt (scalar loads); the face traces go
+  // through the tangential coefficients of the face (face_modes).  This
+  // bounds code size, compile time and live registers.
+  static constexpr bool BIG = (M * V > 100);
+  static constexpr int UQ = BIG ? 1 : S::NQ;    // unroll of volume-point loops
+  static constexpr int US = BIG ? 1 : NS;       // unroll of S_K loops
+  static constexpr int TM = ipow(K + 1, D - 1);
+  using RT = Rt<D, K, SP, T>;
 
   struct State {
     double ub[V];     // cell averages (FP64)
@@ -260,7 +312,10 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
     for (int v = 0; v < V; ++v) {
       T a = T(s.ub[v]);
 #pragma unroll
-      for (int m = 1; m < M; ++m) a = cmad(S::tab.phi_v[q][m], s.ch[v][m - 1], a);
+      for (int m = 1; m < M; ++m) {
+        if constexpr (BIG) a = fma(RT::tab.phi_v[q][m], s.ch[v][m - 1], a);
+        else a = cmad(S::tab.phi_v[q][m], s.ch[v][m - 1], a);
+      }
       u[v] = a;
     }
   }
@@ -277,7 +332,10 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
   __device__ __forceinline__ static double sk_var(const State& s, int p, int v) {
     double a = 0.0;
 #pragma unroll
-    for (int m = 1; m < M; ++m) a = cmad(S::tab.phi_s[p][m], static_cast<double>(s.ch[v][m - 1]), a);
+    for (int m = 1; m < M; ++m) {
+      if constexpr (BIG) a = fma(S::tab.phi_s[p][m], static_cast<double>(s.ch[v][m - 1]), a);
+      else a = cmad(S::tab.phi_s[p][m], static_cast<double>(s.ch[v][m - 1]), a);
+    }
     return s.ub[v] + a;
   }
 
@@ -301,7 +359,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
     T sd[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) sd[d] = T(scale * I.r2dx[d]);
-#pragma unroll
+#pragma unroll UQ
     for (int q = 0; q < S::NQ; ++q) {
       T u[V];
       at_vol(s, q, u);
@@ -314,7 +372,14 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
         for (int v = 0; v < V; ++v) {
           const T g = sd[d] * f[v];
 #pragma unroll
-          for (int m = 1; m < M; ++m) r.ah[v][m - 1] = cmad(S::tab.cvol[q][m][d], g, r.ah[v][m - 1]);
+          for (int m = 1; m < M; ++m) {
+            if constexpr (BIG) {
+              // d phi_m / d xi_d vanishes identically when e_d(m) = 0
+              if (S::modes.e[m][d] != 0) r.ah[v][m - 1] = fma(RT::tab.cvol[q][m][d], g, r.ah[v][m - 1]);
+            } else {
+              r.ah[v][m - 1] = cmad(S::tab.cvol[q][m][d], g, r.ah[v][m - 1]);
+            }
+          }
         }
       }
     }
@@ -338,9 +403,189 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
       }
   }
 
+  // --- faces of the large spaces (BIG), tensor spaces only -----------------
+  // tangential mode of mode m on a face normal to direction d
+  static constexpr int tmode(int m, int d) {
+    int t = 0, mul = 1;
+    for (int j = 0; j < D; ++j)
+      if (j != d) {
+        t += mul * S::modes.e[m][j];
+        mul *= K + 1;
+      }
+    return t;
+  }
+
+  // Coefficients of the trace of a cell on its face f in the tangential
+  // Legendre products: R[v][t] = sum over e_d of P_{e_d}(+-1) c_v(e_d, t),
+  // with P_e(+-1) = (+-1)^e.  get(v, m) returns coefficient m >= 1 and avg(v)
+  // the average.  The operations depend only on the cell's coefficients and
+  // on f, so a cell and its neighbour obtain bitwise the same trace of the
+  // shared face.
+  template <class GetAvg, class GetHi>
+  __device__ __forceinline__ static void face_modes(GetAvg avg, GetHi get, int f, T (&R)[V][TM]) {
+    static_assert(S::TENSOR, "face_modes needs a tensor-product space");
+    const int d = f / 2;
+    const bool up = (f & 1) != 0;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      R[v][0] = T(avg(v));
+#pragma unroll
+      for (int m = 1; m < M; ++m) {
+        const int t = tmode(m, d);
+        const int e = S::modes.e[m][d];
+        const T x = get(v, m);
+        // modes with e_d = 0 come first for every t (ascending mode order)
+        if (e == 0) R[v][t] = x;
+        else if (up || (e % 2) == 0) R[v][t] = R[v][t] + x;
+        else R[v][t] = R[v][t] - x;
+      }
+    }
+  }
+  __device__ __forceinline__ static void face_modes_state(const State& s, int f, T (&R)[V][TM]) {
+    face_modes([&](int v) { return s.ub[v]; }, [&](int v, int m) { return s.ch[v][m - 1]; }, f, R);
+  }
+  __device__ __forceinline__ static void face_modes_mem(const double* avg, const T* hi, int64_t nc,
+                                                        int64_t c, int f, T (&R)[V][TM]) {
+    face_modes([&](int v) { return avg[v * nc + c]; },
+               [&](int v, int m) { return hi[(static_cast<int64_t>(v) * MH + m - 1) * nc + c]; }, f, R);
+  }
+  // trace value at face point b from the tangential coefficients
+  __device__ __forceinline__ static void face_eval(const T (&R)[V][TM], int b, T* u) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      T a = R[v][0];
+#pragma unroll
+      for (int t = 1; t < TM; ++t) a = fma(RT::tab.ftan[b][t], R[v][t], a);
+      u[v] = a;
+    }
+  }
+  // r -= scale / dx_d * (face integral of fn phi_m) for face f, from
+  // H[v][t] = sum_b wb phi_t(b) fn_v(b) and h0[v] = sum_b wb fn_v(b):
+  // phi_m = P_{e_d}(side) phi_t on the face.
+  __device__ __forceinline__ static void face_scatter(int f, const T (&H)[V][TM], const double* h0,
+                                                      const InstDev& I, double scale, Acc& r) {
+    const int d = f / 2;
+    const bool up = (f & 1) != 0;
+    const double sc = scale * I.rdx[d];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      r.a0[v] = fma(up ? -sc : sc, h0[v], r.a0[v]);
+#pragma unroll
+      for (int m = 1; m < M; ++m) {
+        const int e = S::modes.e[m][d];
+        // outward normal sign times P_e(side): side^(e + 1)
+        const bool plus = up || ((e + 1) % 2 == 0);
+        const T c = T((plus ? -sc : sc) * S::pfac(m));
+        r.ah[v][m - 1] = fma(c, H[v][tmode(m, d)], r.ah[v][m - 1]);
+      }
+    }
+  }
+  __device__ __forceinline__ static void face_gather(const T* fn, int b, T (&H)[V][TM], double* h0) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      h0[v] = fma(S::tab.wb[b], static_cast<double>(fn[v]), h0[v]);
+#pragma unroll
+      for (int t = 0; t < TM; ++t) H[v][t] = fma(RT::tab.wftan[b][t], fn[v], H[v][t]);
+    }
+  }
+
+  __device__ __forceinline__ static void op_local_big(const State& s, const InstDev& I, double scale,
+                                                      Acc& r) {
+    volume(s, I, scale, r);
+#pragma unroll
+    for (int f = 0; f < S::NF; ++f) {
+      T R[V][TM];
+      face_modes_state(s, f, R);
+      T H[V][TM];
+      double h0[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        h0[v] = 0.0;
+#pragma unroll
+        for (int t = 0; t < TM; ++t) H[v][t] = T(0);
+      }
+#pragma unroll 1
+      for (int b = 0; b < S::NFP; ++b) {
+        T u[V], fn[V];
+        face_eval(R, b, u);
+        const auto a = P::aux(u, I);
+        P::flux(u, a, f / 2, I, fn);
+        face_gather(fn, b, H, h0);
+      }
+      face_scatter(f, H, h0, I, scale, r);
+    }
+  }
+
+  __device__ __forceinline__ static void op_dg_big(const State& s, const double* avg, const T* hi,
+                                                   int64_t c, const InstDev& I, double scale, Acc& r) {
+    volume(s, I, scale, r);
+#pragma unroll
+    for (int f = 0; f < S::NF; ++f) {
+      const int d = f / 2;
+      const bool upper = (f & 1) != 0;   // this cell is the lower cell of the face
+      const int64_t nb = neighbour(c, f, I);
+      T Ri[V][TM], Re[V][TM];
+      face_modes_state(s, f, Ri);
+      if (nb >= 0) {
+        face_modes_mem(avg, hi, I.ncell, nb, f ^ 1, Re);
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+          for (int t = 0; t < TM; ++t) Re[v][t] = Ri[v][t];
+      }
+      // alpha: largest wave speed over the face points and both traces
+      T alpha = T(0);
+#pragma unroll 1
+      for (int b = 0; b < S::NFP; ++b) {
+        T ui[V], ue[V];
+        face_eval(Ri, b, ui);
+        face_eval(Re, b, ue);
+        const T* uL = upper ? ui : ue;
+        const T* uR = upper ? ue : ui;
+        const auto aL = P::aux(uL, I);
+        const auto aR = P::aux(uR, I);
+        alpha = fmax(alpha, fmax(P::speed(uL, aL, d, I), P::speed(uR, aR, d, I)));
+      }
+      T H[V][TM];
+      double h0[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        h0[v] = 0.0;
+#pragma unroll
+        for (int t = 0; t < TM; ++t) H[v][t] = T(0);
+      }
+#pragma unroll 1
+      for (int b = 0; b < S::NFP; ++b) {
+        T ui[V], ue[V];
+        face_eval(Ri, b, ui);
+        face_eval(Re, b, ue);
+        const T* uL = upper ? ui : ue;
+        const T* uR = upper ? ue : ui;
+        const auto aL = P::aux(uL, I);
+        const auto aR = P::aux(uR, I);
+        T fL[V], fR[V], fn[V];
+        P::flux(uL, aL, d, I, fL);
+        P::flux(uR, aR, d, I, fR);
+        {
+#pragma clang fp contract(off)
+          const T ha = T(0.5) * alpha;
+#pragma unroll
+          for (int v = 0; v < V; ++v) fn[v] = fma(-ha, uR[v] - uL[v], T(0.5) * (fL[v] + fR[v]));
+        }
+        face_gather(fn, b, H, h0);
+      }
+      face_scatter(f, H, h0, I, scale, r);
+    }
+  }
+
   // G = -div^loc f: interior trace flux on every face (Sec. 2.1).
   __device__ __forceinline__ static void op_local(const State& s, const InstDev& I, double scale,
                                                   Acc& r) {
+    if constexpr (BIG) {
+      op_local_big(s, I, scale, r);
+      return;
+    }
     volume(s, I, scale, r);
 #pragma unroll
     for (int f = 0; f < S::NF; ++f) {
@@ -379,6 +624,10 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
   // same value and the averages are updated conservatively.
   __device__ __forceinline__ static void op_dg(const State& s, const double* avg, const T* hi,
                                                int64_t c, const InstDev& I, double scale, Acc& r) {
+    if constexpr (BIG) {
+      op_dg_big(s, avg, hi, c, I, scale, r);
+      return;
+    }
     volume(s, I, scale, r);
 #pragma unroll
     for (int f = 0; f < S::NF; ++f) {
@@ -471,7 +720,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
   // every S_K point inside B (scalar) / B^eps (Euler); FP64 evaluation
   __device__ __forceinline__ static bool points_ok(const State& s, const InstDev& I) {
     bool ok = true;
-#pragma unroll
+#pragma unroll US
     for (int p = 0; p < NS; ++p) {
       if constexpr (SYS == SYS_EULER) {
         const double rho = sk_var(s, p, 0);
@@ -532,14 +781,17 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
         thr_rho *= T(1 + 0x1p-20);
       }
       const T eps = T(I.eps);
-#pragma unroll
+#pragma unroll US
       for (int p = 0; p < NS; ++p) {
         T u[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
           T a = ub[v];
 #pragma unroll
-          for (int m = 1; m < M; ++m) a = cmad(S::tab.phi_s[p][m], s.ch[v][m - 1], a);
+          for (int m = 1; m < M; ++m) {
+            if constexpr (BIG) a = fma(RT::tab.phi_s[p][m], s.ch[v][m - 1], a);
+            else a = cmad(S::tab.phi_s[p][m], s.ch[v][m - 1], a);
+          }
           u[v] = a;
         }
         T ke = T(0);
@@ -557,11 +809,14 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
       }
     } else {
       const double lo = I.blo, hi = I.bhi;
-#pragma unroll
+#pragma unroll US
       for (int p = 0; p < NS; ++p) {
         T a = ub[0];
 #pragma unroll
-        for (int m = 1; m < M; ++m) a = cmad(S::tab.phi_s[p][m], s.ch[0][m - 1], a);
+        for (int m = 1; m < M; ++m) {
+          if constexpr (BIG) a = fma(RT::tab.phi_s[p][m], s.ch[0][m - 1], a);
+          else a = cmad(S::tab.phi_s[p][m], s.ch[0][m - 1], a);
+        }
         const double u = static_cast<double>(a);
         const double e = static_cast<double>(err[0]);
         ok = ok && (u - e >= lo) && (u + e <= hi);
@@ -618,7 +873,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
       const double eps = I.eps;
       const double rb = s.ub[0];
       double rmin = INFINITY;
-#pragma unroll
+#pragma unroll US
       for (int p = 0; p < NS; ++p) rmin = fmin(rmin, sk_var(s, p, 0));
       double th1 = 1.0;
       if (!(rmin >= eps)) {
@@ -627,7 +882,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
       }
       // internal energy of the density-limited polynomial: cheap test first
       bool low = false;
-#pragma unroll
+#pragma unroll US
       for (int p = 0; p < NS; ++p) {
         const double r0 = sk_var(s, p, 0);
         const double rho = (th1 == 1.0) ? r0 : rb + th1 * (r0 - rb);
@@ -666,7 +921,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
     } else {
       const double ub = s.ub[0];
       double mx = -INFINITY, mn = INFINITY;
-#pragma unroll
+#pragma unroll US
       for (int p = 0; p < NS; ++p) {
         const double u = sk_var(s, p, 0);
         mx = fmax(mx, u);
@@ -998,7 +1253,7 @@ __global__ __launch_bounds__(BLOCK) void k_project(KArgs a) {
     double acc[C::M];
 #pragma unroll
     for (int m = 0; m < C::M; ++m) acc[m] = 0.0;
-#pragma unroll
+#pragma unroll C::UQ
     for (int q = 0; q < S::NQ; ++q) {
       const double x = smp[(v * I.ncell + c) * S::NQ + q];
 #pragma unroll
