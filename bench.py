@@ -1,20 +1,27 @@
 """Benchmark of the cRKDG hot path on one MI355X.
 
-Workload: 2D compressible Euler on a periodic 1024 x 1024 mesh, tensor Q^2
-modal DG (9 modes x 4 variables), 3-stage cRKDG (Heun's third-order method)
-with the limiter after every stage, seeded 64-site Voronoi states
-(rho in [1e-3, 1], p in [1e-6, 10], |w| <= 3).  One step = all stages
-(local stages with G, final stage with F and Lax--Friedrichs fluxes, the
-scaling limiter after each, the fused CFL wave-speed maximum) plus the device
-step controller, for the whole mesh.
+Headline workload: 2D compressible Euler on a periodic 1024 x 1024 mesh,
+tensor Q^2 modal DG (9 modes x 4 variables), 3-stage cRKDG (Heun's
+third-order method) with the limiter after every stage, seeded 64-site
+Voronoi states (rho in [1e-3, 1], p in [1e-6, 10], |w| <= 3).  One step = all
+stages (local stages with G, final stage with F and Lax--Friedrichs fluxes,
+the scaling limiter after each, the fused CFL wave-speed maximum) plus the
+device step controller, for the whole mesh.
 
 The headline `value` is the mixed-precision form (FP32 modes >= 1, FP64
 averages / checks / limiter theta / average update); the plain FP64 form is
 timed on the same workload and reported beside it with the relative L1
 difference of the two after the same number of steps.
 
-Metric: DOF-stage updates/s = Nc * M * V * executed stages / wall time, with
-the state resident in HBM before the timed region starts.
+Two more workloads are measured in the same run and reported under
+"workloads" (a failure there is reported, never fatal to the headline):
+  euler3d  3D Euler, 128^3 periodic, Q^2 (27 modes x 5 variables), RK4
+           cRKDG, smooth translating density wave (rho = 1 + 0.99 sin);
+  batched  64 independent 2D Euler instances in one mesh, N_i ~ U{64..512},
+           P^1-P^3, 3 or 4 stages, 16-site Voronoi states, per-instance dt.
+
+Metric: DOF-stage updates/s = sum over instances of Nc M V x executed stages
+/ wall time, with the state resident in HBM before the timed region starts.
 """
 from __future__ import annotations
 
@@ -24,6 +31,7 @@ import math
 import os
 import sys
 import time
+import traceback
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -31,15 +39,23 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
 
+# states the final stage reads besides writing one: u~^n plus every u~^(j),
+# j >= 2, with b_j != 0 (Heun3: b_2 = 0; RK2: b_1 = 0 but u~^n is the base)
+FINAL_READS = {2: 2, 3: 2, 4: 4}
+# algorithmic state transfers per step (Scheme 1L): reads + writes of all stages
+STEP_STATES = {2: 5, 3: 8, 4: 13}
+
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=1024, help="cells per direction")
+    ap.add_argument("--n", type=int, default=1024, help="cells per direction of the headline workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--workloads", default="euler3d,batched",
+                    help="extra workloads to measure (comma list of euler3d, batched; empty for none)")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (to scale HBM byte counters)")
@@ -50,18 +66,50 @@ def state_bytes(nvars, nmodes, mixed):
     return nvars * (8 + (4 if mixed else 8) * (nmodes - 1))
 
 
-def setup(case, precision, crkdg, torch):
-    params = dict(case.params, precision=precision)
-    mesh = crkdg.Mesh(crkdg.problem_from_params(params))
+# ---------------------------------------------------------------------------
+# workload set-up (synthetic, seeded; state resident on the device)
+# ---------------------------------------------------------------------------
+def wave3d_state(mesh, state, case, n, torch):
+    """Samples of the smooth 3D wave at every volume Gauss point, made on the
+    device, projected by the library."""
+    xq = torch.from_numpy(mesh.points(0, 0)[:, :3]).cuda()
+    Q = xq.shape[0]
+    c = (torch.arange(n, device="cuda", dtype=torch.float64) + 0.5) / n
+    h = 0.5 / n
+    X = c.view(1, 1, n, 1) + h * xq[:, 0].view(1, 1, 1, Q)
+    Y = c.view(1, n, 1, 1) + h * xq[:, 1].view(1, 1, 1, Q)
+    Z = c.view(n, 1, 1, 1) + h * xq[:, 2].view(1, 1, 1, Q)
+    rho = 1.0 + 0.99 * torch.sin(2.0 * math.pi * (X + Y + Z).reshape(-1, Q) + case.meta["phase"])
+    smp = torch.empty((5, n ** 3, Q), dtype=torch.float64, device="cuda")
+    for v in range(1, 4):
+        smp[v] = rho
+    smp[0] = rho
+    smp[4] = 2.5 + 1.5 * rho          # p = 1, gamma = 1.4, w = (1, 1, 1)
+    mesh.project(smp.reshape(-1), state)
+
+
+def setup(name, precision, crkdg, inputs, torch, n2d):
+    if name == "euler2d":
+        cases = [inputs.euler_2d_voronoi(seed=0, n=n2d)]
+    elif name == "euler3d":
+        cases = [inputs.euler_3d_wave(seed=0, n=128)]
+    else:
+        cases = inputs.batched_2d(seed=0)
+    probs = [crkdg.problem_from_params(dict(c.params, precision=precision)) for c in cases]
+    mesh = crkdg.Mesh(probs)
     slots = mesh.new_slots()
-    a, h = mesh.views(slots[0])
-    a.copy_(torch.from_numpy(case.cell_states.T.copy()))
-    h.zero_()
+    if name == "euler3d":
+        wave3d_state(mesh, slots[0], cases[0], 128, torch)
+    else:
+        for i, c in enumerate(cases):
+            a, h = mesh.views(slots[0], inst=i)
+            a.copy_(torch.from_numpy(c.cell_states.T.copy()))
+            h.zero_()
     ctl = mesh.new_ctl()
     mesh.limit(slots[0], ctl)
     mesh.start(slots, ctl)
     torch.cuda.synchronize()
-    return mesh, slots, ctl
+    return cases, mesh, slots, ctl
 
 
 def run_steps(mesh, slots, ctl, k, torch, stream):
@@ -79,8 +127,9 @@ def run_steps(mesh, slots, ctl, k, torch, stream):
 
 
 def time_kernels(mesh, slots, ctl, reps, torch, stream):
-    """Average duration (ms) of each stage kernel, launched alone through
-    crkdg_stage on the same buffers, timed with HIP events on its stream."""
+    """Average duration (ms) of each stage (its kernel plus the deferred
+    limiter kernel that completes it), launched alone through crkdg_stage on
+    the same buffers, timed with HIP events on its stream (one instance)."""
     s = mesh.problems[0].stages
     c = mesh.ctl_read(ctl)[0]
     cur = c["cur"]
@@ -104,16 +153,46 @@ def time_kernels(mesh, slots, ctl, reps, torch, stream):
     return res
 
 
-def kernel_source_hash():
-    """Hash of the HIP sources, to tell whether committed counter data still
-    describe the kernels that run."""
-    import hashlib
-    from pathlib import Path
-    h = hashlib.sha256()
-    for f in sorted((Path(ROOT) / "paper_2412_16002_amd" / "csrc").glob("*")):
-        h.update(f.name.encode())
-        h.update(f.read_bytes())
-    return h.hexdigest()[:16]
+def measure(name, precision, args, crkdg, inputs, torch, stream, kernels=True):
+    cases, mesh, slots, ctl = setup(name, precision, crkdg, inputs, torch, args.n)
+    run_steps(mesh, slots, ctl, args.warmup, torch, stream)
+    c0 = mesh.ctl_read(ctl)
+    ms = run_steps(mesh, slots, ctl, args.steps, torch, stream)
+    c1 = mesh.ctl_read(ctl)
+    mixed = precision == "mixed"
+    dof_stages = 0
+    step_bytes = 0
+    for i, L in enumerate(mesh.inst):
+        dof = L["n_cells"] * L["n_modes"] * L["n_vars"]
+        dof_stages += dof * (c1[i]["stages_run"] - c0[i]["stages_run"])
+        S = state_bytes(L["n_vars"], L["n_modes"], mixed)
+        step_bytes += STEP_STATES[L["n_stages"]] * S * L["n_cells"] * (c1[i]["accepted"] - c0[i]["accepted"]
+                                                                      + c1[i]["rejected"] - c0[i]["rejected"])
+    r = dict(ms=ms, value=dof_stages / (ms / 1e3),
+             accepted=sum(c1[i]["accepted"] - c0[i]["accepted"] for i in range(len(c1))),
+             rejected=sum(c1[i]["rejected"] - c0[i]["rejected"] for i in range(len(c1))),
+             step_hbm_fraction=step_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+             t=[c["t"] for c in c1], cur=[c["cur"] for c in c1])
+    if kernels and len(mesh.inst) == 1:
+        r["kern"] = time_kernels(mesh, slots, ctl, args.kernel_reps, torch, stream)
+        L = mesh.inst[0]
+        s = L["n_stages"]
+        S = state_bytes(L["n_vars"], L["n_modes"], mixed)
+        alg = (FINAL_READS[s] + 1) * S * L["n_cells"]
+        kfin = r["kern"][s + 1]
+        r["final"] = dict(alg_bytes=alg, kernel_ms=kfin, achieved=alg / (kfin / 1e3) / 1e9)
+    return r, mesh, slots
+
+
+def l1_diff(mesh_a, slots_a, cur_a, mesh_b, slots_b, cur_b, torch):
+    """max over instances and variables of sum |avg_a - avg_b| / sum |avg_b|."""
+    worst = 0.0
+    for i in range(len(mesh_a.inst)):
+        a, _ = mesh_a.views(slots_a[cur_a[i]], inst=i)
+        b, _ = mesh_b.views(slots_b[cur_b[i]], inst=i)
+        d = (a - b).abs().sum(dim=1) / b.abs().sum(dim=1)
+        worst = max(worst, float(d.max()))
+    return worst
 
 
 def measured_traffic():
@@ -128,11 +207,22 @@ def measured_traffic():
     return d["traffic_bytes_per_launch"] if d.get("source_hash") == kernel_source_hash() else None
 
 
+def kernel_source_hash():
+    """Hash of the HIP sources, to tell whether committed counter data still
+    describe the kernels that run."""
+    import hashlib
+    from pathlib import Path
+    h = hashlib.sha256()
+    for f in sorted((Path(ROOT) / "paper_2412_16002_amd" / "csrc").glob("*")):
+        h.update(f.name.encode())
+        h.update(f.read_bytes())
+    return h.hexdigest()[:16]
+
+
 def cpu_baseline(case, budget_s=20.0):
     """The oracle, as it is, on a bounded sample of the same workload: a
     periodic 96 x 96 sub-mesh with the same kind of data, one step at a time
     until ~budget_s of CPU time, single thread."""
-    import numpy as np
     from threadpoolctl import threadpool_limits
 
     import oracle
@@ -162,6 +252,30 @@ def cpu_baseline(case, budget_s=20.0):
                       f"{steps} full steps in {el:.1f} s, FP64 numpy, 1 thread"}
 
 
+def extra_workload(name, args, crkdg, inputs, torch, stream):
+    """Mixed and FP64 runs of one extra workload (step throughput, final-stage
+    roofline for single-instance meshes, mixed vs FP64 difference)."""
+    out = {}
+    finals = {}
+    for prec in ("mixed", "fp64"):
+        r, mesh, slots = measure(name, prec, args, crkdg, inputs, torch, stream)
+        finals[prec] = (mesh, slots, r["cur"])
+        e = {"value": r["value"], "ms_per_step": r["ms"] / args.steps, "accepted_steps": r["accepted"],
+             "rejected_attempts": r["rejected"], "step_hbm_fraction": r["step_hbm_fraction"]}
+        if "kern" in r:
+            e["kernel_ms"] = {f"stage{i}": v for i, v in r["kern"].items()}
+            f = r["final"]
+            e["final_stage_roofline"] = {"bound": "hbm", "achieved": f["achieved"], "peak": HBM_PEAK_GBS,
+                                         "unit": "GB/s", "frac": f["achieved"] / HBM_PEAK_GBS,
+                                         "alg_bytes_per_launch": f["alg_bytes"], "kernel_ms": f["kernel_ms"]}
+        out[prec] = e
+    out["speedup_mixed_vs_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
+    mm, sm, cm = finals["mixed"]
+    mf, sf, cf = finals["fp64"]
+    out["l1_rel_avg_mixed_vs_fp64"] = l1_diff(mm, sm, cm, mf, sf, cf, torch)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -169,7 +283,6 @@ def main():
                                    "note (see the design document), not an implemented path",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
-    import numpy as np
     import torch
 
     from paper_2412_16002_amd import crkdg, inputs
@@ -186,7 +299,6 @@ def main():
         print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 3}), flush=True)
         return
     stream = torch.cuda.current_stream()
-    case = inputs.euler_2d_voronoi(seed=0, n=args.n)
     Nc = args.n * args.n
     M, V, s = 9, 4, 3
     dof = Nc * M * V
@@ -194,32 +306,15 @@ def main():
     results = {}
     finals = {}
     for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):
-        mesh, slots, ctl = setup(case, prec, crkdg, torch)
-        run_steps(mesh, slots, ctl, args.warmup, torch, stream)
-        c0 = mesh.ctl_read(ctl)[0]
-        ms = run_steps(mesh, slots, ctl, args.steps, torch, stream)
-        c1 = mesh.ctl_read(ctl)[0]
-        stages_run = c1["stages_run"] - c0["stages_run"]
-        accepted = c1["accepted"] - c0["accepted"]
-        rejected = c1["rejected"] - c0["rejected"]
-        kern = time_kernels(mesh, slots, ctl, args.kernel_reps, torch, stream)
-        finals[prec] = (mesh, slots, c1)
-        results[prec] = dict(ms=ms, stages_run=stages_run, accepted=accepted, rejected=rejected,
-                             kern=kern, t=c1["t"], status=c1["status"])
+        r, mesh, slots = measure("euler2d", prec, args, crkdg, inputs, torch, stream)
+        results[prec] = r
+        finals[prec] = (mesh, slots, r["cur"])
 
     mixed = results["mixed"]
-    value = dof * mixed["stages_run"] / (mixed["ms"] / 1e3)
-    S = state_bytes(V, M, True)
-    # dominant kernel: the final stage (reads u~^n and u~^(3), writes
-    # u~^{n+1}); its event time covers the stage kernel and the deferred
-    # limiter kernel that completes it (plus a ~2 us queue-counter reset)
-    kfin = mixed["kern"][s + 1]
-    alg_bytes = 3 * S * Nc
-    achieved = alg_bytes / (kfin / 1e3) / 1e9
-    step_bytes = 8 * S * Nc   # Heun3 Scheme 1L: 2S + 3S + 3S per step
+    fin = mixed["final"]
     line = {
         "metric": "DOF-stage updates/s",
-        "value": value,
+        "value": mixed["value"],
         "unit": "DOF-stage updates/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -236,29 +331,38 @@ def main():
         "accepted_steps": mixed["accepted"],
         "rejected_attempts": mixed["rejected"],
         "kernel_ms": {f"stage{i}": v for i, v in mixed["kern"].items()},
-        "step_hbm_fraction": (step_bytes / (mixed["ms"] / args.steps / 1e3) / 1e9) / HBM_PEAK_GBS,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+        "step_hbm_fraction": mixed["step_hbm_fraction"],
+        # dominant kernel: the final stage (reads u~^n and u~^(3), writes
+        # u~^{n+1}); its event time covers the stage kernel and the deferred
+        # limiter kernel that completes it (plus a ~2 us queue-counter reset)
+        "roofline": {"bound": "hbm", "achieved": fin["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": fin["achieved"] / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_stage_final<2,2,Q,Euler,float> + k_limit_queue<...,final>",
-                     "alg_bytes_per_launch": alg_bytes, "kernel_ms": kfin},
+                     "alg_bytes_per_launch": fin["alg_bytes"], "kernel_ms": fin["kernel_ms"]},
     }
     if "fp64" in results:
         f = results["fp64"]
-        v64 = dof * f["stages_run"] / (f["ms"] / 1e3)
-        line["fp64"] = {"value": v64, "ms_per_step": f["ms"] / args.steps,
+        line["fp64"] = {"value": f["value"], "ms_per_step": f["ms"] / args.steps,
                         "kernel_ms": {f"stage{i}": v for i, v in f["kern"].items()},
                         "accepted_steps": f["accepted"], "rejected_attempts": f["rejected"]}
-        line["speedup_mixed_vs_fp64"] = value / v64
-        # relative L1 difference of the cell averages after the same number of attempts
-        mm, ms_, cm = finals["mixed"]
+        line["speedup_mixed_vs_fp64"] = mixed["value"] / f["value"]
+        mm, sm, cm = finals["mixed"]
         mf, sf, cf = finals["fp64"]
-        am, _ = mm.views(ms_[cm["cur"]])
-        af, _ = mf.views(sf[cf["cur"]])
-        diff = (am - af).abs().sum(dim=1) / af.abs().sum(dim=1)
-        line["l1_rel_avg_mixed_vs_fp64"] = float(diff.max())
-        line["t_mixed_vs_fp64"] = [cm["t"], cf["t"]]
+        line["l1_rel_avg_mixed_vs_fp64"] = l1_diff(mm, sm, cm, mf, sf, cf, torch)
+        line["t_mixed_vs_fp64"] = [mixed["t"][0], f["t"][0]]
+    del finals
+    torch.cuda.empty_cache()
+    extra = {}
+    for name in [w for w in args.workloads.split(",") if w]:
+        try:
+            extra[name] = extra_workload(name, args, crkdg, inputs, torch, stream)
+        except Exception as e:  # reported, never fatal to the headline line
+            extra[name] = {"error": f"{type(e).__name__}: {e}", "trace": traceback.format_exc()[-600:]}
+        torch.cuda.empty_cache()
+    if extra:
+        line["workloads"] = extra
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(case)
+        line["cpu_baseline"] = cpu_baseline(inputs.euler_2d_voronoi(seed=0, n=args.n))
     print(json.dumps(line), flush=True)
 
 

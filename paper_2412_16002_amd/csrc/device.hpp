@@ -14,6 +14,7 @@
 #include <cfloat>
 #include <cmath>
 #include <cstdint>
+#include <utility>
 
 #include "crkdg.h"
 #include "tables.hpp"
@@ -153,6 +154,18 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// fn(std::integral_constant<int, i>) for i = 0 .. N-1, expanded at compile
+// time whatever the size of the body (a plain unrolled loop may stay a loop
+// when its body is large)
+template <class Fn, int... I>
+__device__ __forceinline__ void static_for_impl(Fn&& fn, std::integer_sequence<int, I...>) {
+  (fn(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class Fn>
+__device__ __forceinline__ void static_for(Fn&& fn) {
+  static_for_impl(fn, std::make_integer_sequence<int, N>{});
+}
+
 // ---------------------------------------------------------------------------
 // physics (Sec. 2.2.3 for Euler)
 // ---------------------------------------------------------------------------
@@ -228,9 +241,13 @@ template <int D, int K, int SP, typename T> struct RtTab {
   T phi_v[S::NQ][S::M];
   T cvol[S::NQ][S::M][D];
   T phi_s[S::NS_RAW][S::M];
+  T cface[S::NF][S::NFP][S::M];
   T ftan[S::NFP][TM];    // tangential Legendre products at the face points
   T wftan[S::NFP][TM];   // the same times the face weight
-  constexpr RtTab() : phi_v{}, cvol{}, phi_s{}, ftan{}, wftan{} {
+  constexpr RtTab() : phi_v{}, cvol{}, phi_s{}, cface{}, ftan{}, wftan{} {
+    for (int f = 0; f < S::NF; ++f)
+      for (int b = 0; b < S::NFP; ++b)
+        for (int m = 0; m < S::M; ++m) cface[f][b][m] = static_cast<T>(S::tab.cface[f][b][m]);
     for (int q = 0; q < S::NQ; ++q)
       for (int m = 0; m < S::M; ++m) {
         phi_v[q][m] = static_cast<T>(S::tab.phi_v[q][m]);
@@ -480,6 +497,19 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
       }
     }
   }
+  // r -= scale / dx_d * cface[f][b][m] fn(b) for one face point b of face f
+  __device__ __forceinline__ static void face_point_scatter(int f, int b, const T* fn, const InstDev& I,
+                                                            double scale, Acc& r) {
+    const double sc = scale * I.rdx[f / 2];
+    const double w = sc * S::tab.cface[f][b][0];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      r.a0[v] = fma(-w, static_cast<double>(fn[v]), r.a0[v]);
+      const T g = T(-sc) * fn[v];
+#pragma unroll
+      for (int m = 1; m < M; ++m) r.ah[v][m - 1] = fma(RT::tab.cface[f][b][m], g, r.ah[v][m - 1]);
+    }
+  }
   __device__ __forceinline__ static void face_gather(const T* fn, int b, T (&H)[V][TM], double* h0) {
 #pragma unroll
     for (int v = 0; v < V; ++v) {
@@ -492,40 +522,31 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
   __device__ __forceinline__ static void op_local_big(const State& s, const InstDev& I, double scale,
                                                       Acc& r) {
     volume(s, I, scale, r);
-#pragma unroll
-    for (int f = 0; f < S::NF; ++f) {
+    static_for<S::NF>([&](auto F) {
+      constexpr int f = decltype(F)::value;
       T R[V][TM];
       face_modes_state(s, f, R);
-      T H[V][TM];
-      double h0[V];
-#pragma unroll
-      for (int v = 0; v < V; ++v) {
-        h0[v] = 0.0;
-#pragma unroll
-        for (int t = 0; t < TM; ++t) H[v][t] = T(0);
-      }
 #pragma unroll 1
       for (int b = 0; b < S::NFP; ++b) {
         T u[V], fn[V];
         face_eval(R, b, u);
         const auto a = P::aux(u, I);
         P::flux(u, a, f / 2, I, fn);
-        face_gather(fn, b, H, h0);
+        face_point_scatter(f, b, fn, I, scale, r);
       }
-      face_scatter(f, H, h0, I, scale, r);
-    }
+    });
   }
 
   __device__ __forceinline__ static void op_dg_big(const State& s, const double* avg, const T* hi,
                                                    int64_t c, const InstDev& I, double scale, Acc& r) {
     volume(s, I, scale, r);
-#pragma unroll
-    for (int f = 0; f < S::NF; ++f) {
-      const int d = f / 2;
-      const bool upper = (f & 1) != 0;   // this cell is the lower cell of the face
+    static_for<S::NF>([&](auto F) {
+      constexpr int f = decltype(F)::value;
+      constexpr int d = f / 2;
+      constexpr bool upper = (f & 1) != 0;   // this cell is the lower cell of the face
       const int64_t nb = neighbour(c, f, I);
       T Ri[V][TM], Re[V][TM];
-      face_modes_state(s, f, Ri);
+      face_modes_mem(avg, hi, I.ncell, c, f, Ri);
       if (nb >= 0) {
         face_modes_mem(avg, hi, I.ncell, nb, f ^ 1, Re);
       } else {
@@ -547,14 +568,6 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
         const auto aR = P::aux(uR, I);
         alpha = fmax(alpha, fmax(P::speed(uL, aL, d, I), P::speed(uR, aR, d, I)));
       }
-      T H[V][TM];
-      double h0[V];
-#pragma unroll
-      for (int v = 0; v < V; ++v) {
-        h0[v] = 0.0;
-#pragma unroll
-        for (int t = 0; t < TM; ++t) H[v][t] = T(0);
-      }
 #pragma unroll 1
       for (int b = 0; b < S::NFP; ++b) {
         T ui[V], ue[V];
@@ -573,10 +586,9 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
 #pragma unroll
           for (int v = 0; v < V; ++v) fn[v] = fma(-ha, uR[v] - uL[v], T(0.5) * (fL[v] + fR[v]));
         }
-        face_gather(fn, b, H, h0);
+        face_point_scatter(f, b, fn, I, scale, r);
       }
-      face_scatter(f, H, h0, I, scale, r);
-    }
+    });
   }
 
   // G = -div^loc f: interior trace flux on every face (Sec. 2.1).
