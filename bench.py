@@ -153,12 +153,38 @@ def time_kernels(mesh, slots, ctl, reps, torch, stream):
     return res
 
 
-def measure(name, precision, args, crkdg, inputs, torch, stream, kernels=True):
+def run_graph(graph, torch, stream):
+    """One launch of a step graph; elapsed ms from HIP events on the stream."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    graph.launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def measure(name, precision, args, crkdg, inputs, torch, stream, kernels=True, batched=False):
+    """batched: autotune the launch shapes, then run warm-up and timed steps
+    as two captured step graphs (one launch each)."""
     cases, mesh, slots, ctl = setup(name, precision, crkdg, inputs, torch, args.n)
-    run_steps(mesh, slots, ctl, args.warmup, torch, stream)
-    c0 = mesh.ctl_read(ctl)
-    ms = run_steps(mesh, slots, ctl, args.steps, torch, stream)
-    c1 = mesh.ctl_read(ctl)
+    tuning = None
+    if batched:
+        tuning = mesh.autotune(slots, ctl, reps=2)
+        gw = mesh.graph(slots, ctl, attempts=args.warmup)
+        gt = mesh.graph(slots, ctl, attempts=args.steps)
+        run_graph(gw, torch, stream)
+        c0 = mesh.ctl_read(ctl)
+        ms = run_graph(gt, torch, stream)
+        c1 = mesh.ctl_read(ctl)
+        gw.close()
+        gt.close()
+    else:
+        run_steps(mesh, slots, ctl, args.warmup, torch, stream)
+        c0 = mesh.ctl_read(ctl)
+        ms = run_steps(mesh, slots, ctl, args.steps, torch, stream)
+        c1 = mesh.ctl_read(ctl)
     mixed = precision == "mixed"
     dof_stages = 0
     step_bytes = 0
@@ -173,6 +199,9 @@ def measure(name, precision, args, crkdg, inputs, torch, stream, kernels=True):
              rejected=sum(c1[i]["rejected"] - c0[i]["rejected"] for i in range(len(c1))),
              step_hbm_fraction=step_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
              t=[c["t"] for c in c1], cur=[c["cur"] for c in c1])
+    if tuning is not None:
+        r["tuning"] = [{k: t[k] for k in ("dim", "k", "stages", "n_inst", "n_cells", "threads", "tile_x",
+                                          "grid", "ms")} for t in tuning]
     if kernels and len(mesh.inst) == 1:
         r["kern"] = time_kernels(mesh, slots, ctl, args.kernel_reps, torch, stream)
         L = mesh.inst[0]
@@ -258,10 +287,13 @@ def extra_workload(name, args, crkdg, inputs, torch, stream):
     out = {}
     finals = {}
     for prec in ("mixed", "fp64"):
-        r, mesh, slots = measure(name, prec, args, crkdg, inputs, torch, stream)
+        r, mesh, slots = measure(name, prec, args, crkdg, inputs, torch, stream, batched=(name == "batched"))
         finals[prec] = (mesh, slots, r["cur"])
         e = {"value": r["value"], "ms_per_step": r["ms"] / args.steps, "accepted_steps": r["accepted"],
              "rejected_attempts": r["rejected"], "step_hbm_fraction": r["step_hbm_fraction"]}
+        if "tuning" in r:
+            e["launch"] = "autotuned shapes; warm-up and timed attempts as two captured step graphs"
+            e["tuning"] = r["tuning"]
         if "kern" in r:
             e["kernel_ms"] = {f"stage{i}": v for i, v in r["kern"].items()}
             f = r["final"]

@@ -262,6 +262,62 @@ int crkdg_stage(crkdg_mesh *mesh, int32_t stage, const crkdg_state *states, int3
 int crkdg_step(crkdg_mesh *mesh, const crkdg_state *slots, int32_t n_slots, crkdg_ctl *d_ctl,
                crkdg_step_info *info, void *stream);
 
+/* ---- launch shapes, autotuning and step graphs ------------------------
+ * The instances of a mesh fall into kernel groups: one group per compiled
+ * variant (dim, k, space, system, precision) and stage count.  The stage
+ * kernels of a group (crkdg_stage, crkdg_step) run with one launch shape:
+ * workgroups of `threads` threads, each tile of `tile_x` x (threads / tile_x)
+ * cells of one x-y plane (1D: `threads` consecutive cells), walked in an
+ * XCD-ordered map either by one workgroup per tile (grid = 0) or by a
+ * persistent grid of `grid` workgroups.  The shape changes which thread
+ * handles which cell, never the arithmetic: results are bitwise identical
+ * for every shape. */
+typedef struct crkdg_tuning {
+  int32_t threads;   /* 64, 128 or 256 */
+  int32_t tile_x;    /* 2D/3D: power of two in [8, threads]; 1D: = threads */
+  int32_t grid;      /* 0: one workgroup per tile; else a multiple of 8 */
+  int32_t dim, k, space, stages, n_inst; /* read only: the group */
+  int32_t n_items;   /* read only: tiles in the group's map */
+  int32_t pad;
+  int64_t n_cells;   /* read only: cells of the group */
+  double ms;         /* read only: stage time of one attempt measured by crkdg_autotune */
+} crkdg_tuning;
+
+/* Number of kernel groups of the mesh. */
+int crkdg_group_count(const crkdg_mesh *mesh, int32_t *n_groups);
+
+/* Current launch shape of group `group` (default: 256 threads, 32-wide
+ * tiles, one workgroup per tile). */
+int crkdg_get_tuning(const crkdg_mesh *mesh, int32_t group, crkdg_tuning *out);
+
+/* Set the launch shape of group `group` from threads, tile_x and grid
+ * (CRKDG_E_ARG when out of range).  Synchronous (uploads the tile map). */
+int crkdg_set_tuning(crkdg_mesh *mesh, int32_t group, const crkdg_tuning *t);
+
+/* Autotuner: for every group, time `reps` passes of its stage kernels over
+ * the slot ring (as crkdg_step would run them, without the controller) for
+ * each candidate shape (threads 64/128/256, tile widths 8..64, one workgroup
+ * per tile or persistent grids of 1024 and 2048) and keep the fastest.  Call
+ * after crkdg_start: the passes read u~^n = slots[d_ctl.cur] and write only
+ * the other slots; d_ctl and the internal queues are restored afterwards, so
+ * the next crkdg_step proceeds exactly as without tuning.  Synchronous. */
+int crkdg_autotune(crkdg_mesh *mesh, const crkdg_state *slots, int32_t n_slots, crkdg_ctl *d_ctl,
+                   int32_t reps, void *stream);
+
+/* A HIP graph of `attempts` consecutive crkdg_step attempts (info == NULL
+ * form) on these slots and controllers, with the current launch shapes.
+ * Launching it is equivalent to calling crkdg_step(..., NULL, stream)
+ * `attempts` times; instances that finished skip the remaining attempts on
+ * the device.  The buffers must outlive the graph, and the graph must be
+ * destroyed before the mesh; while a graph of the mesh exists,
+ * crkdg_set_tuning and crkdg_autotune fail with CRKDG_E_ARG (the graph uses
+ * the mesh's tile maps). */
+typedef struct crkdg_graph crkdg_graph;
+int crkdg_graph_create(crkdg_mesh *mesh, const crkdg_state *slots, int32_t n_slots, crkdg_ctl *d_ctl,
+                       int32_t attempts, crkdg_graph **out);
+int crkdg_graph_launch(crkdg_graph *graph, void *stream);
+int crkdg_graph_destroy(crkdg_graph *graph);
+
 #ifdef __cplusplus
 }
 #endif

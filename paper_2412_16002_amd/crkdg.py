@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import math
+import weakref
 from dataclasses import dataclass, field
 from pathlib import Path
 
@@ -67,6 +68,12 @@ class CStepInfo(C.Structure):
                 ("cur", C.c_int32), ("pad", C.c_int32), ("accepted", C.c_int64), ("rejected", C.c_int64)]
 
 
+class CTuning(C.Structure):
+    _fields_ = [("threads", C.c_int32), ("tile_x", C.c_int32), ("grid", C.c_int32), ("dim", C.c_int32),
+                ("k", C.c_int32), ("space", C.c_int32), ("stages", C.c_int32), ("n_inst", C.c_int32),
+                ("n_items", C.c_int32), ("pad", C.c_int32), ("n_cells", C.c_int64), ("ms", C.c_double)]
+
+
 def _load():
     if not _LIB_PATH.exists():
         raise ImportError(f"{_LIB_PATH} is not built: run `python -m paper_2412_16002_amd.build`")
@@ -89,6 +96,14 @@ def _load():
                                   C.c_void_p]),
         "crkdg_step": (C.c_int, [C.c_void_p, P(CState), C.c_int32, C.c_void_p, P(CStepInfo),
                                  C.c_void_p]),
+        "crkdg_group_count": (C.c_int, [C.c_void_p, P(C.c_int32)]),
+        "crkdg_get_tuning": (C.c_int, [C.c_void_p, C.c_int32, P(CTuning)]),
+        "crkdg_set_tuning": (C.c_int, [C.c_void_p, C.c_int32, P(CTuning)]),
+        "crkdg_autotune": (C.c_int, [C.c_void_p, P(CState), C.c_int32, C.c_void_p, C.c_int32, C.c_void_p]),
+        "crkdg_graph_create": (C.c_int, [C.c_void_p, P(CState), C.c_int32, C.c_void_p, C.c_int32,
+                                         P(C.c_void_p)]),
+        "crkdg_graph_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
+        "crkdg_graph_destroy": (C.c_int, [C.c_void_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -100,7 +115,9 @@ def _load():
 LIB = _load()
 EXPORTED = ("crkdg_last_error", "crkdg_init_mesh", "crkdg_free_mesh", "crkdg_instance_query",
             "crkdg_points", "crkdg_project", "crkdg_limit", "crkdg_cell_avg", "crkdg_cfl",
-            "crkdg_start", "crkdg_stage", "crkdg_step")
+            "crkdg_start", "crkdg_stage", "crkdg_step", "crkdg_group_count", "crkdg_get_tuning",
+            "crkdg_set_tuning", "crkdg_autotune", "crkdg_graph_create", "crkdg_graph_launch",
+            "crkdg_graph_destroy")
 
 
 class CRKDGError(RuntimeError):
@@ -226,6 +243,8 @@ class Mesh:
         assert lay.ctl_bytes == C.sizeof(CCtl), "crkdg_ctl size mismatch between header and binding"
 
     def close(self):
+        for g in list(getattr(self, "_graphs", ())):
+            g.close()
         if self.h:
             LIB.crkdg_free_mesh(self.h)
             self.h = None
@@ -370,3 +389,61 @@ class Mesh:
         for o in out:
             o["rc"] = rc
         return out
+
+    # ---------------- launch shapes, autotuning, step graphs ----------------
+    def group_count(self):
+        n = C.c_int32()
+        _check(LIB.crkdg_group_count(self.h, C.byref(n)), "crkdg_group_count")
+        return n.value
+
+    def get_tuning(self, group=0):
+        t = CTuning()
+        _check(LIB.crkdg_get_tuning(self.h, group, C.byref(t)), "crkdg_get_tuning")
+        return {f: getattr(t, f) for f, _ in CTuning._fields_}
+
+    def set_tuning(self, group, threads, tile_x, grid=0):
+        t = CTuning()
+        t.threads, t.tile_x, t.grid = threads, tile_x, grid
+        _check(LIB.crkdg_set_tuning(self.h, group, C.byref(t)), "crkdg_set_tuning")
+
+    def autotune(self, slots, ctl, reps=3):
+        cs = (CState * len(slots))(*[s.c() for s in slots])
+        _check(LIB.crkdg_autotune(self.h, cs, len(slots), C.c_void_p(ctl.data_ptr()), reps, _stream()),
+               "crkdg_autotune")
+        return [self.get_tuning(g) for g in range(self.group_count())]
+
+    def graph(self, slots, ctl, attempts=1):
+        """A StepGraph of `attempts` asynchronous step attempts on these buffers."""
+        return StepGraph(self, slots, ctl, attempts)
+
+
+class StepGraph:
+    """crkdg_graph handle: launch() enqueues the captured attempts on the
+    current stream.  Keeps the mesh and buffers alive; close() before the
+    mesh is freed."""
+
+    def __init__(self, mesh, slots, ctl, attempts):
+        self.mesh, self.slots, self.ctl = mesh, list(slots), ctl
+        cs = (CState * len(self.slots))(*[s.c() for s in self.slots])
+        h = C.c_void_p()
+        _check(LIB.crkdg_graph_create(mesh.h, cs, len(self.slots), C.c_void_p(ctl.data_ptr()), attempts,
+                                      C.byref(h)), "crkdg_graph_create")
+        self.h = h
+        self.attempts = attempts
+        if not hasattr(mesh, "_graphs"):
+            mesh._graphs = weakref.WeakSet()
+        mesh._graphs.add(self)
+
+    def launch(self):
+        _check(LIB.crkdg_graph_launch(self.h, _stream()), "crkdg_graph_launch")
+
+    def close(self):
+        if self.h:
+            LIB.crkdg_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -46,11 +46,13 @@ struct InstDev {
   double gamma, blo, bhi, eps, cfl, vol;
 };
 
-// One workgroup = one tile of cells of one instance: BLOCK consecutive cells
-// in 1D, a TILE_X x TILE_Y tile of one x-y plane in 2D/3D (a wavefront then
-// covers TILE_X x 64/TILE_X cells: full 128-byte row segments of the FP32
-// arrays, both face neighbours close, and fewer wavefronts crossed by a
-// discontinuity than with 64-cell row segments).
+// One work item = one tile of cells of one instance: blockDim.x consecutive
+// cells in 1D, a tile_x x (blockDim.x / tile_x) tile of one x-y plane in
+// 2D/3D.  The default 32 x 8 tile of a 256-thread workgroup gives every
+// wavefront 32 x 2 cells: full 128-byte row segments of the FP32 arrays, both
+// face neighbours close, and fewer wavefronts crossed by a discontinuity than
+// with 64-cell row segments.  The stage kernels take their tile shape,
+// workgroup size and grid from the group's tuning (crkdg_autotune).
 struct BlockItem {
   int32_t inst;
   int32_t lblock;    // logical block number (fixed order for reductions)
@@ -58,17 +60,17 @@ struct BlockItem {
   int32_t z, pad;
 };
 constexpr int TILE_X = 32;
-constexpr int TILE_Y = BLOCK / TILE_X;
+constexpr int TILE_SHIFT = 5;   // log2 TILE_X
 
 __device__ __forceinline__ int64_t tile_cell(const BlockItem& bi, int dim, const int32_t* n,
-                                             int64_t ncell, bool& active) {
+                                             int64_t ncell, int shift, bool& active) {
   if (dim == 1) {
     const int64_t c = static_cast<int64_t>(bi.x0) + threadIdx.x;
     active = c < ncell;
     return c;
   }
-  const int x = bi.x0 + static_cast<int>(threadIdx.x % TILE_X);
-  const int y = bi.y0 + static_cast<int>(threadIdx.x / TILE_X);
+  const int x = bi.x0 + static_cast<int>(threadIdx.x & ((1u << shift) - 1u));
+  const int y = bi.y0 + static_cast<int>(threadIdx.x >> shift);
   active = x < n[0] && y < n[1];
   return x + static_cast<int64_t>(n[0]) * (y + static_cast<int64_t>(n[1]) * bi.z);
 }
@@ -94,6 +96,8 @@ struct KArgs {
   void* queue;         // records of the cells whose limiter is deferred
   unsigned* qcount;    // number of queued cells of this stage
   unsigned qcap;       // record capacity of the queue (cells of the group)
+  int32_t n_items;     // entries of bmap
+  int32_t tile_shift;  // log2 of the tile width (2D/3D)
 };
 
 // ---------------------------------------------------------------------------
@@ -1032,9 +1036,8 @@ __device__ __forceinline__ T* hi_ptr(void* p, int64_t off) {
 // Inner stage i = 2..s (Scheme 1L): out = L(base + dt a G(in)); flags on a
 // non-admissible unlimited average.
 template <int D, int K, int SP, int SYS, typename T>
-__global__ __launch_bounds__(BLOCK) void k_stage_local(KArgs a) {
+__device__ __forceinline__ void stage_local_item(const KArgs& a, const BlockItem& bi) {
   using C = Cell<D, K, SP, SYS, T>;
-  const BlockItem bi = a.bmap[blockIdx.x];
   if (bi.inst < 0) return;  // padding entry of the XCD-ordered block map
   const InstDev& I = a.inst[bi.inst];
   crkdg_ctl* ctl = a.ctl + bi.inst;
@@ -1053,7 +1056,7 @@ __global__ __launch_bounds__(BLOCK) void k_stage_local(KArgs a) {
   const double dt = ctl->dt;
 
   bool active;
-  const int64_t c = tile_cell(bi, D, I.n, I.ncell, active);
+  const int64_t c = tile_cell(bi, D, I.n, I.ncell, a.tile_shift, active);
   bool bad = false, nonfin = false;
   if (active) {
     typename C::State u;
@@ -1074,12 +1077,19 @@ __global__ __launch_bounds__(BLOCK) void k_stage_local(KArgs a) {
   raise_flag(&ctl->flags, nonfin, CRKDG_F_NONFINITE);
 }
 
+// The stage kernels walk the tiles of their block map with a grid stride: a
+// grid of one workgroup per tile, or a persistent grid (a multiple of 8, so
+// that a workgroup stays on one XCD's run of tiles).
+template <int D, int K, int SP, int SYS, typename T>
+__global__ __launch_bounds__(BLOCK) void k_stage_local(KArgs a) {
+  for (int it = blockIdx.x; it < a.n_items; it += gridDim.x) stage_local_item<D, K, SP, SYS, T>(a, a.bmap[it]);
+}
+
 // Final stage (Scheme 1L): out = L(base + dt sum_j b_j F(u~^(j))); also the
 // wave speeds of the limited result for the next trial step.
 template <int D, int K, int SP, int SYS, typename T>
-__global__ __launch_bounds__(BLOCK) void k_stage_final(KArgs a) {
+__device__ __forceinline__ void stage_final_item(const KArgs& a, const BlockItem& bi) {
   using C = Cell<D, K, SP, SYS, T>;
-  const BlockItem bi = a.bmap[blockIdx.x];
   if (bi.inst < 0) return;  // padding entry of the XCD-ordered block map
   const InstDev& I = a.inst[bi.inst];
   crkdg_ctl* ctl = a.ctl + bi.inst;
@@ -1095,7 +1105,7 @@ __global__ __launch_bounds__(BLOCK) void k_stage_final(KArgs a) {
   T* o_hi = hi_ptr<T>(sel_hi(a.slots, sl_out), I.hi_off);
 
   bool active;
-  const int64_t c = tile_cell(bi, D, I.n, I.ncell, active);
+  const int64_t c = tile_cell(bi, D, I.n, I.ncell, a.tile_shift, active);
   bool bad = false, nonfin = false;
   double a0[D];
 #pragma unroll
@@ -1146,6 +1156,11 @@ __global__ __launch_bounds__(BLOCK) void k_stage_final(KArgs a) {
       atomicMax(reinterpret_cast<unsigned long long*>(&ctl->a0_next[d]),
                 static_cast<unsigned long long>(__double_as_longlong(m)));
   }
+}
+
+template <int D, int K, int SP, int SYS, typename T>
+__global__ __launch_bounds__(BLOCK) void k_stage_final(KArgs a) {
+  for (int it = blockIdx.x; it < a.n_items; it += gridDim.x) stage_final_item<D, K, SP, SYS, T>(a, a.bmap[it]);
 }
 
 // Limiter of the cells a stage kernel queued (same slot rotation as the
@@ -1201,7 +1216,7 @@ __global__ __launch_bounds__(BLOCK) void k_limit(KArgs a) {
   double* avg = a.slots.avg[0] + I.avg_off;
   T* hi = hi_ptr<T>(a.slots.hi[0], I.hi_off);
   bool active;
-  const int64_t c = tile_cell(bi, D, I.n, I.ncell, active);
+  const int64_t c = tile_cell(bi, D, I.n, I.ncell, a.tile_shift, active);
   bool bad = false;
   if (active) {
     typename C::State u;
@@ -1227,7 +1242,7 @@ __global__ __launch_bounds__(BLOCK) void k_cfl(KArgs a) {
   const double* avg = sel_avg(a.slots, cur) + I.avg_off;
   const T* hi = hi_ptr<T>(sel_hi(a.slots, cur), I.hi_off);
   bool active;
-  const int64_t c = tile_cell(bi, D, I.n, I.ncell, active);
+  const int64_t c = tile_cell(bi, D, I.n, I.ncell, a.tile_shift, active);
   double a0[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) a0[d] = 0.0;
@@ -1257,7 +1272,7 @@ __global__ __launch_bounds__(BLOCK) void k_project(KArgs a) {
   T* hi = hi_ptr<T>(a.slots.hi[0], I.hi_off);
   const double* smp = a.samples + I.avg_off * S::NQ;
   bool active;
-  const int64_t c = tile_cell(bi, D, I.n, I.ncell, active);
+  const int64_t c = tile_cell(bi, D, I.n, I.ncell, a.tile_shift, active);
   if (!active) return;
   typename C::State u;
 #pragma unroll

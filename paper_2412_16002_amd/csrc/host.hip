@@ -70,12 +70,25 @@ const VariantOps* find_ops(int dim, int k, int space, int system, int precision)
   return nullptr;
 }
 
+// Launch shape of the stage kernels of one group (see crkdg_tuning).
+struct Tune {
+  int threads = BLOCK;          // workgroup size
+  int tile_x = TILE_X;          // tile width (2D/3D); 1D: = threads
+  int grid = 0;                 // 0: one workgroup per tile; else persistent grid
+  double ms = 0.0;              // measured by the autotuner
+};
+
 struct Group {
   const VariantOps* ops;
   int stages;
+  int dim;
   std::vector<int> insts;
-  int nblocks = 0;              // grid size (a multiple of 8, padded)
-  BlockItem* d_bmap = nullptr;
+  int nblocks = 0;              // default map: grid size (a multiple of 8, padded)
+  BlockItem* d_bmap = nullptr;  // default map (256 threads, 32 x 8 tiles): all but the stage kernels
+  Tune tune;                    // stage kernels
+  int n_items = 0;              // entries of the stage map
+  int smap_cap = 0;             // allocated entries of the stage map
+  BlockItem* d_smap = nullptr;  // stage map (tiles of the tuned shape, XCD order)
   int64_t ncells = 0;           // cells of all instances of the group
   int64_t queue_off = 0;        // byte offset of the group's deferred-limiter queue
   unsigned qcap = 0;            // its record capacity
@@ -98,6 +111,7 @@ struct crkdg_mesh {
   int total_lblocks = 0;
   int max_stages = 0;
   int device = 0;
+  int live_graphs = 0;          // step graphs holding this mesh's stage maps
 };
 
 namespace {
@@ -120,6 +134,38 @@ std::vector<BlockItem> xcd_block_map(const std::vector<BlockItem>& logical) {
     if (l < nl) phys[b] = logical[l];
   }
   return phys;
+}
+
+// Logical tiles of one instance for workgroups of `threads` threads and tiles
+// `tile_x` cells wide (2D/3D), z-plane by z-plane, rows of tiles x fastest.
+void instance_tiles(const crkdg_problem& p, int inst, int threads, int tile_x, int& lblock,
+                    std::vector<BlockItem>& out) {
+  int64_t nc = 1;
+  for (int d = 0; d < p.dim; ++d) nc *= p.n[d];
+  const int tx_cells = (p.dim == 1) ? threads : tile_x;
+  const int ty_cells = (p.dim == 1) ? 1 : threads / tile_x;
+  const int64_t tx = (p.dim == 1) ? (nc + threads - 1) / threads : (p.n[0] + tx_cells - 1) / tx_cells;
+  const int64_t ty = (p.dim == 1) ? 1 : (p.n[1] + ty_cells - 1) / ty_cells;
+  const int64_t tz = (p.dim == 3) ? p.n[2] : 1;
+  for (int64_t z = 0; z < tz; ++z)
+    for (int64_t y = 0; y < ty; ++y)
+      for (int64_t x = 0; x < tx; ++x) {
+        BlockItem it{};
+        it.inst = inst;
+        it.lblock = lblock++;
+        it.x0 = static_cast<int32_t>(x * tx_cells);
+        it.y0 = static_cast<int32_t>(y * ty_cells);
+        it.z = static_cast<int32_t>(z);
+        out.push_back(it);
+      }
+}
+
+int64_t instance_tile_count(const crkdg_problem& p, int threads, int tile_x) {
+  int64_t nc = 1;
+  for (int d = 0; d < p.dim; ++d) nc *= p.n[d];
+  if (p.dim == 1) return (nc + threads - 1) / threads;
+  const int ty_cells = threads / tile_x;
+  return ((p.n[0] + tile_x - 1) / tile_x) * ((p.n[1] + ty_cells - 1) / ty_cells) * (p.dim == 3 ? p.n[2] : 1);
 }
 
 int validate(const crkdg_problem& p, int idx) {
@@ -230,7 +276,7 @@ __global__ __launch_bounds__(BLOCK) void k_totals_partial(const InstDev* inst, c
   const InstDev& I = inst[bi.inst];
   __shared__ double sh[BLOCK];
   bool active;
-  const int64_t c = tile_cell(bi, I.dim, I.n, I.ncell, active);
+  const int64_t c = tile_cell(bi, I.dim, I.n, I.ncell, TILE_SHIFT, active);
   for (int v = 0; v < V; ++v) {
     sh[threadIdx.x] = active ? I.vol * avg[I.avg_off + v * I.ncell + c] : 0.0;
     __syncthreads();
@@ -276,8 +322,61 @@ KArgs base_args(const crkdg_mesh* m, const Group& g, crkdg_ctl* ctl) {
   KArgs a{};
   a.inst = m->d_inst;
   a.bmap = g.d_bmap;
+  a.n_items = g.nblocks;
+  a.tile_shift = TILE_SHIFT;
   a.ctl = ctl;
   return a;
+}
+
+int ilog2(int x) {
+  int r = 0;
+  while ((1 << r) < x) ++r;
+  return r;
+}
+
+// Check a launch shape for a group: workgroups of 64, 128 or 256 threads;
+// 2D/3D tiles a power of two between 8 and the workgroup size wide; a
+// persistent grid a positive multiple of 8.
+int check_tune(const Group& g, const Tune& t) {
+  if (t.threads != 64 && t.threads != 128 && t.threads != 256)
+    return fail(CRKDG_E_ARG, "threads must be 64, 128 or 256");
+  if (g.dim == 1) {
+    if (t.tile_x != t.threads) return fail(CRKDG_E_ARG, "1D: tile_x must equal threads");
+  } else if (t.tile_x < 8 || t.tile_x > t.threads || (t.tile_x & (t.tile_x - 1)) != 0) {
+    return fail(CRKDG_E_ARG, "tile_x must be a power of two in [8, threads]");
+  }
+  if (t.grid < 0 || t.grid % 8 != 0) return fail(CRKDG_E_ARG, "grid must be 0 or a positive multiple of 8");
+  return CRKDG_OK;
+}
+
+// Build and upload the stage map of group gi for launch shape t (synchronous).
+int apply_tune(crkdg_mesh* m, int gi, const Tune& t) {
+  Group& g = m->groups[gi];
+  if (int rc = check_tune(g, t)) return rc;
+  if (m->live_graphs > 0)
+    return fail(CRKDG_E_ARG, "launch shapes are fixed while a step graph of the mesh exists");
+  std::vector<BlockItem> logical;
+  int lb = 0;
+  for (int i : g.insts) instance_tiles(m->probs[i], i, t.threads, t.tile_x, lb, logical);
+  std::vector<BlockItem> phys = xcd_block_map(logical);
+  const int n = static_cast<int>(phys.size());
+  if (n > g.smap_cap) {
+    if (g.d_smap) HIP_TRY(hipFree(g.d_smap));
+    g.d_smap = nullptr;
+    g.smap_cap = 0;
+    HIP_TRY(hipMalloc(&g.d_smap, sizeof(BlockItem) * n));
+    g.smap_cap = n;
+  }
+  HIP_TRY(hipMemcpy(g.d_smap, phys.data(), sizeof(BlockItem) * n, hipMemcpyHostToDevice));
+  g.n_items = n;
+  g.tune = t;
+  return CRKDG_OK;
+}
+
+// Grid of the stage kernels: one workgroup per tile, or the persistent grid
+// (never more workgroups than tiles).
+int stage_grid(const Group& g) {
+  return (g.tune.grid > 0) ? std::min(g.tune.grid, g.n_items) : g.n_items;
 }
 
 int n_vars_of(int system, int dim) { return system == CRKDG_SYS_EULER ? dim + 2 : 1; }
@@ -387,27 +486,16 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
       g = it->second;
     }
     m->groups[g].insts.push_back(i);
-    const int64_t tx = (p.dim == 1) ? (nc + BLOCK - 1) / BLOCK : (p.n[0] + TILE_X - 1) / TILE_X;
-    const int64_t ty = (p.dim == 1) ? 1 : (p.n[1] + TILE_Y - 1) / TILE_Y;
-    const int64_t tz = (p.dim == 3) ? p.n[2] : 1;
-    const int64_t nb = tx * ty * tz;
-    if (nb + lblock > (int64_t(1) << 30)) {
+    m->groups[g].dim = p.dim;
+    // the smallest tiles any tuning may use (64 threads) must stay countable
+    const int64_t nb = instance_tile_count(p, BLOCK, TILE_X);
+    if (nb + lblock > (int64_t(1) << 30) || instance_tile_count(p, 64, 8) > (int64_t(1) << 30)) {
       delete m;
       return fail(CRKDG_E_ARG, "too many cells in total");
     }
     I.first_block = lblock;
     I.n_blocks = static_cast<int>(nb);
-    for (int64_t z = 0; z < tz; ++z)
-      for (int64_t y = 0; y < ty; ++y)
-        for (int64_t x = 0; x < tx; ++x) {
-          BlockItem it{};
-          it.inst = i;
-          it.lblock = lblock++;
-          it.x0 = static_cast<int32_t>(p.dim == 1 ? x * BLOCK : x * TILE_X);
-          it.y0 = static_cast<int32_t>(y * TILE_Y);
-          it.z = static_cast<int32_t>(z);
-          logical[g].push_back(it);
-        }
+    instance_tiles(p, i, BLOCK, TILE_X, lblock, logical[g]);
   }
   m->total_lblocks = lblock;
 
@@ -428,6 +516,15 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
     if ((e = hipMalloc(&G.d_bmap, sizeof(BlockItem) * phys.size())) != hipSuccess) return cleanup("hipMalloc", e);
     if ((e = hipMemcpy(G.d_bmap, phys.data(), sizeof(BlockItem) * phys.size(), hipMemcpyHostToDevice)) != hipSuccess)
       return cleanup("hipMemcpy", e);
+  }
+
+  for (size_t g = 0; g < m->groups.size(); ++g) {
+    Tune t;
+    if (m->groups[g].dim == 1) t.tile_x = t.threads;
+    if (int rc = apply_tune(m, static_cast<int>(g), t)) {
+      crkdg_free_mesh(m);
+      return rc;
+    }
   }
 
   // deferred-limiter queue: one record per cell of the group, so a stage
@@ -466,8 +563,10 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
 int crkdg_free_mesh(crkdg_mesh* m) {
   if (!m) return CRKDG_OK;
   hipSetDevice(m->device);
-  for (Group& g : m->groups)
+  for (Group& g : m->groups) {
     if (g.d_bmap) hipFree(g.d_bmap);
+    if (g.d_smap) hipFree(g.d_smap);
+  }
   if (m->d_inst) hipFree(m->d_inst);
   if (m->d_partial) hipFree(m->d_partial);
   if (m->d_queue) hipFree(m->d_queue);
@@ -550,7 +649,7 @@ int crkdg_project(crkdg_mesh* m, const double* d_samples, crkdg_state out, void*
     a.slots.avg[0] = out.avg;
     a.slots.hi[0] = out.hi;
     a.samples = d_samples;
-    g.ops->project(a, g.nblocks, s);
+    g.ops->project(a, g.nblocks, BLOCK, s);
   }
   HIP_TRY(hipGetLastError());
   return CRKDG_OK;
@@ -565,7 +664,7 @@ int crkdg_limit(crkdg_mesh* m, crkdg_state u, crkdg_ctl* d_ctl, void* stream) {
     KArgs a = base_args(m, g, d_ctl);
     a.slots.avg[0] = u.avg;
     a.slots.hi[0] = u.hi;
-    g.ops->limit(a, g.nblocks, s);
+    g.ops->limit(a, g.nblocks, BLOCK, s);
   }
   HIP_TRY(hipGetLastError());
   return CRKDG_OK;
@@ -610,7 +709,7 @@ static int launch_cfl(crkdg_mesh* m, const crkdg_state* slots, int nslots, int r
     }
     a.slots.n = nslots;
     a.slots.rotate = rotate;
-    g.ops->cfl(a, g.nblocks, s);
+    g.ops->cfl(a, g.nblocks, BLOCK, s);
   }
   hipLaunchKernelGGL(k_a0_finish, dim3((n + 63) / 64), dim3(64), 0, s, d_ctl, m->d_inst, n);
   HIP_TRY(hipGetLastError());
@@ -660,6 +759,9 @@ static int launch_stage(crkdg_mesh* m, int gi, int stage, const Slots& slots, cr
     return fail(CRKDG_E_ARG, "stage index out of range");
   const Butcher bt = butcher(g.stages);
   KArgs a = base_args(m, g, d_ctl);
+  a.bmap = g.d_smap;
+  a.n_items = g.n_items;
+  a.tile_shift = ilog2(g.tune.tile_x);
   a.slots = slots;
   a.stage = stage;
   a.queue = m->d_queue + g.queue_off;
@@ -669,14 +771,15 @@ static int launch_stage(crkdg_mesh* m, int gi, int stage, const Slots& slots, cr
   // (crkdg_stage clears its own after the stage)
   // the queue holds a few percent of the cells: up to 256 workgroups drain it
   const int qblocks = static_cast<int>(std::min<int64_t>(256, (g.ncells + BLOCK - 1) / BLOCK));
+  const int grid = stage_grid(g);
   if (stage <= g.stages) {
     a.a = bt.a[stage];
-    g.ops->stage_local(a, g.nblocks, s);
-    g.ops->queue_local(a, qblocks, s);
+    g.ops->stage_local(a, grid, g.tune.threads, s);
+    g.ops->queue_local(a, qblocks, BLOCK, s);
   } else {
     for (int j = 0; j < 4; ++j) a.b[j] = bt.b[j];
-    g.ops->stage_final(a, g.nblocks, s);
-    g.ops->queue_final(a, qblocks, s);
+    g.ops->stage_final(a, grid, g.tune.threads, s);
+    g.ops->queue_final(a, qblocks, BLOCK, s);
   }
   return CRKDG_OK;
 }
@@ -780,6 +883,219 @@ int crkdg_step(crkdg_mesh* m, const crkdg_state* slots, int32_t n_slots, crkdg_c
     if (h[i].status == CRKDG_S_DT_UNDERFLOW || h[i].status == CRKDG_S_NONFINITE) ret = h[i].status;
   }
   return ret;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// launch shapes of the stage kernels, the autotuner, and step graphs
+// ---------------------------------------------------------------------------
+namespace {
+
+void tune_out(const Group& g, crkdg_tuning* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->threads = g.tune.threads;
+  o->tile_x = g.tune.tile_x;
+  o->grid = g.tune.grid;
+  o->dim = g.dim;
+  o->k = g.ops->k;
+  o->space = g.ops->space;
+  o->stages = g.stages;
+  o->n_inst = static_cast<int32_t>(g.insts.size());
+  o->n_items = g.n_items;
+  o->n_cells = g.ncells;
+  o->ms = g.tune.ms;
+}
+
+// the stage kernels of one group for one attempt, without the controller;
+// the group's deferred-limiter counters are cleared afterwards
+int group_pass(crkdg_mesh* m, int gi, const Slots& sl, crkdg_ctl* d_ctl, hipStream_t s) {
+  const Group& g = m->groups[gi];
+  for (int stage = 2; stage <= g.stages + 1; ++stage)
+    if (int rc = launch_stage(m, gi, stage, sl, d_ctl, s)) return rc;
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, m->d_qcount + gi * QSTAGES, QSTAGES);
+  HIP_TRY(hipGetLastError());
+  return CRKDG_OK;
+}
+
+std::vector<Tune> candidates(const Group& g) {
+  std::vector<Tune> out;
+  const int grids[] = {0, 1024, 2048};
+  for (int th : {256, 128, 64}) {
+    std::vector<int> widths;
+    if (g.dim == 1) widths.push_back(th);
+    else
+      for (int w = 8; w <= std::min(th, 64); w *= 2) widths.push_back(w);
+    for (int w : widths)
+      for (int gr : grids) {
+        Tune t;
+        t.threads = th;
+        t.tile_x = w;
+        t.grid = gr;
+        out.push_back(t);
+      }
+  }
+  return out;
+}
+
+int slots_from(const crkdg_mesh* m, const crkdg_state* slots, int32_t n_slots, Slots& sl) {
+  if (!slots) return fail(CRKDG_E_ARG, "slots is NULL");
+  if (n_slots < m->layout.n_slots || n_slots > MAX_SLOTS)
+    return fail(CRKDG_E_LAYOUT, "n_slots must be layout.n_slots");
+  sl = Slots{};
+  for (int j = 0; j < n_slots; ++j) {
+    if (int rc = check_state(slots[j], "slot")) return rc;
+    sl.avg[j] = slots[j].avg;
+    sl.hi[j] = slots[j].hi;
+  }
+  sl.n = n_slots;
+  sl.rotate = 1;
+  return CRKDG_OK;
+}
+
+}  // namespace
+
+struct crkdg_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  crkdg_mesh* mesh = nullptr;
+  int device = 0;
+};
+
+extern "C" {
+
+int crkdg_group_count(const crkdg_mesh* m, int32_t* n_groups) {
+  if (check_mesh(m)) return CRKDG_E_ARG;
+  if (!n_groups) return fail(CRKDG_E_ARG, "n_groups is NULL");
+  *n_groups = static_cast<int32_t>(m->groups.size());
+  return CRKDG_OK;
+}
+
+int crkdg_get_tuning(const crkdg_mesh* m, int32_t group, crkdg_tuning* out) {
+  if (check_mesh(m)) return CRKDG_E_ARG;
+  if (group < 0 || group >= static_cast<int>(m->groups.size()) || !out)
+    return fail(CRKDG_E_ARG, "bad group index");
+  tune_out(m->groups[group], out);
+  return CRKDG_OK;
+}
+
+int crkdg_set_tuning(crkdg_mesh* m, int32_t group, const crkdg_tuning* t) {
+  if (check_mesh(m)) return CRKDG_E_ARG;
+  if (group < 0 || group >= static_cast<int>(m->groups.size()) || !t)
+    return fail(CRKDG_E_ARG, "bad group index");
+  if (int rc = set_device(m)) return rc;
+  Tune u;
+  u.threads = t->threads;
+  u.tile_x = t->tile_x;
+  u.grid = t->grid;
+  return apply_tune(m, group, u);
+}
+
+int crkdg_autotune(crkdg_mesh* m, const crkdg_state* slots, int32_t n_slots, crkdg_ctl* d_ctl,
+                   int32_t reps, void* stream) {
+  if (check_mesh(m)) return CRKDG_E_ARG;
+  if (!d_ctl) return fail(CRKDG_E_ARG, "d_ctl is NULL");
+  if (reps < 1 || reps > 1000) return fail(CRKDG_E_ARG, "reps must be 1..1000");
+  Slots sl;
+  if (int rc = slots_from(m, slots, n_slots, sl)) return rc;
+  if (int rc = set_device(m)) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n = m->layout.n_inst;
+  std::vector<crkdg_ctl> saved(n);
+  HIP_TRY(hipMemcpyAsync(saved.data(), d_ctl, sizeof(crkdg_ctl) * n, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int rc = CRKDG_OK;
+  for (int gi = 0; gi < static_cast<int>(m->groups.size()) && rc == CRKDG_OK; ++gi) {
+    Tune best = m->groups[gi].tune;
+    double best_ms = INFINITY;
+    for (const Tune& t : candidates(m->groups[gi])) {
+      if ((rc = apply_tune(m, gi, t))) break;
+      if ((rc = group_pass(m, gi, sl, d_ctl, s))) break;   // warm-up
+      if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(CRKDG_E_HIP, "hipEventRecord"); break; }
+      for (int r = 0; r < reps && rc == CRKDG_OK; ++r) rc = group_pass(m, gi, sl, d_ctl, s);
+      if (rc) break;
+      float ms = 0.0f;
+      if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = fail(CRKDG_E_HIP, "event timing failed");
+        break;
+      }
+      if (ms / reps < best_ms) {
+        best_ms = ms / reps;
+        best = t;
+      }
+    }
+    if (rc == CRKDG_OK) {
+      best.ms = best_ms;
+      rc = apply_tune(m, gi, best);
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  // the tuning passes wrote only stage slots, never slot cur; the
+  // controllers and the queue counters go back to their state before
+  HIP_TRY(hipMemcpyAsync(d_ctl, saved.data(), sizeof(crkdg_ctl) * n, hipMemcpyHostToDevice, s));
+  const int nq = static_cast<int>(m->groups.size()) * QSTAGES;
+  hipLaunchKernelGGL(k_zero_u32, dim3((nq + 63) / 64), dim3(64), 0, s, m->d_qcount, nq);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  return rc;
+}
+
+int crkdg_graph_create(crkdg_mesh* m, const crkdg_state* slots, int32_t n_slots, crkdg_ctl* d_ctl,
+                       int32_t attempts, crkdg_graph** out) {
+  if (check_mesh(m)) return CRKDG_E_ARG;
+  if (!d_ctl || !out) return fail(CRKDG_E_ARG, "NULL argument");
+  if (attempts < 1 || attempts > 4096) return fail(CRKDG_E_ARG, "attempts must be 1..4096");
+  *out = nullptr;
+  Slots sl;
+  if (int rc = slots_from(m, slots, n_slots, sl)) return rc;
+  if (int rc = set_device(m)) return rc;
+  hipStream_t cs;
+  HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  auto* g = new crkdg_graph();
+  g->device = m->device;
+  int rc = CRKDG_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    rc = fail(CRKDG_E_HIP, "hipStreamBeginCapture failed");
+  } else {
+    for (int a = 0; a < attempts && rc == CRKDG_OK; ++a) rc = enqueue_attempt(m, sl, d_ctl, cs);
+    const hipError_t e = hipStreamEndCapture(cs, &g->graph);
+    if (rc == CRKDG_OK && e != hipSuccess) rc = fail(CRKDG_E_HIP, "hipStreamEndCapture failed");
+  }
+  if (rc == CRKDG_OK && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess)
+    rc = fail(CRKDG_E_HIP, "hipGraphInstantiate failed");
+  hipStreamDestroy(cs);
+  if (rc != CRKDG_OK) {
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    delete g;
+    return rc;
+  }
+  g->mesh = m;
+  ++m->live_graphs;
+  *out = g;
+  return CRKDG_OK;
+}
+
+int crkdg_graph_launch(crkdg_graph* g, void* stream) {
+  if (!g) return fail(CRKDG_E_ARG, "graph is NULL");
+  HIP_TRY(hipSetDevice(g->device));
+  HIP_TRY(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+  return CRKDG_OK;
+}
+
+int crkdg_graph_destroy(crkdg_graph* g) {
+  if (!g) return CRKDG_OK;
+  hipSetDevice(g->device);
+  if (g->exec) hipGraphExecDestroy(g->exec);
+  if (g->graph) hipGraphDestroy(g->graph);
+  if (g->mesh) --g->mesh->live_graphs;
+  delete g;
+  return CRKDG_OK;
 }
 
 }  // extern "C"

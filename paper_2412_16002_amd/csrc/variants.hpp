@@ -6,7 +6,8 @@
 
 namespace crkdg {
 
-using Launch = void (*)(const KArgs&, int nblocks, hipStream_t);
+// grid workgroups of `threads` threads
+using Launch = void (*)(const KArgs&, int grid, int threads, hipStream_t);
 
 struct VariantOps {
   int dim, k, space, system, precision;
@@ -17,26 +18,26 @@ struct VariantOps {
 
 template <int D, int K, int SP, int SYS, typename T> struct Ops {
   using C = Cell<D, K, SP, SYS, T>;
-  static void stage_local(const KArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_stage_local<D, K, SP, SYS, T>), dim3(nb), dim3(BLOCK), 0, s, a);
+  static void stage_local(const KArgs& a, int nb, int nt, hipStream_t s) {
+    hipLaunchKernelGGL((k_stage_local<D, K, SP, SYS, T>), dim3(nb), dim3(nt), 0, s, a);
   }
-  static void stage_final(const KArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_stage_final<D, K, SP, SYS, T>), dim3(nb), dim3(BLOCK), 0, s, a);
+  static void stage_final(const KArgs& a, int nb, int nt, hipStream_t s) {
+    hipLaunchKernelGGL((k_stage_final<D, K, SP, SYS, T>), dim3(nb), dim3(nt), 0, s, a);
   }
-  static void limit(const KArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_limit<D, K, SP, SYS, T>), dim3(nb), dim3(BLOCK), 0, s, a);
+  static void limit(const KArgs& a, int nb, int nt, hipStream_t s) {
+    hipLaunchKernelGGL((k_limit<D, K, SP, SYS, T>), dim3(nb), dim3(nt), 0, s, a);
   }
-  static void cfl(const KArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_cfl<D, K, SP, SYS, T>), dim3(nb), dim3(BLOCK), 0, s, a);
+  static void cfl(const KArgs& a, int nb, int nt, hipStream_t s) {
+    hipLaunchKernelGGL((k_cfl<D, K, SP, SYS, T>), dim3(nb), dim3(nt), 0, s, a);
   }
-  static void project(const KArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_project<D, K, SP, SYS, T>), dim3(nb), dim3(BLOCK), 0, s, a);
+  static void project(const KArgs& a, int nb, int nt, hipStream_t s) {
+    hipLaunchKernelGGL((k_project<D, K, SP, SYS, T>), dim3(nb), dim3(nt), 0, s, a);
   }
-  static void queue_local(const KArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_limit_queue<D, K, SP, SYS, T, false>), dim3(nb), dim3(BLOCK), 0, s, a);
+  static void queue_local(const KArgs& a, int nb, int nt, hipStream_t s) {
+    hipLaunchKernelGGL((k_limit_queue<D, K, SP, SYS, T, false>), dim3(nb), dim3(nt), 0, s, a);
   }
-  static void queue_final(const KArgs& a, int nb, hipStream_t s) {
-    hipLaunchKernelGGL((k_limit_queue<D, K, SP, SYS, T, true>), dim3(nb), dim3(BLOCK), 0, s, a);
+  static void queue_final(const KArgs& a, int nb, int nt, hipStream_t s) {
+    hipLaunchKernelGGL((k_limit_queue<D, K, SP, SYS, T, true>), dim3(nb), dim3(nt), 0, s, a);
   }
   static VariantOps make() {
     return VariantOps{D, K, SP, SYS, sizeof(T) == 8 ? CRKDG_FP64 : CRKDG_MIXED,

@@ -50,7 +50,8 @@ def test_struct_layouts_match_header(tmp_path):
     from paper_2412_16002_amd import crkdg
     mirrors = {"crkdg_problem": crkdg.CProblem, "crkdg_layout": crkdg.CLayout,
                "crkdg_instance_layout": crkdg.CInstLayout, "crkdg_state": crkdg.CState,
-               "crkdg_ctl": crkdg.CCtl, "crkdg_step_info": crkdg.CStepInfo}
+               "crkdg_ctl": crkdg.CCtl, "crkdg_step_info": crkdg.CStepInfo,
+               "crkdg_tuning": crkdg.CTuning}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "crkdg.h"', "int main(void) {"]
     for cname, py in mirrors.items():
         lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
