@@ -241,14 +241,13 @@ template <int D, int SYS> struct Phys {
 // ---------------------------------------------------------------------------
 template <int D, int K, int SP, typename T> struct RtTab {
   using S = Space<D, K, SP>;
-  static constexpr int TM = ipow(K + 1, D - 1);  // tangential modes of a face
+  static constexpr int TM = S::TM;
   T phi_v[S::NQ][S::M];
   T cvol[S::NQ][S::M][D];
   T phi_s[S::NS_RAW][S::M];
   T cface[S::NF][S::NFP][S::M];
   T ftan[S::NFP][TM];    // tangential Legendre products at the face points
-  T wftan[S::NFP][TM];   // the same times the face weight
-  constexpr RtTab() : phi_v{}, cvol{}, phi_s{}, cface{}, ftan{}, wftan{} {
+  constexpr RtTab() : phi_v{}, cvol{}, phi_s{}, cface{}, ftan{} {
     for (int f = 0; f < S::NF; ++f)
       for (int b = 0; b < S::NFP; ++b)
         for (int m = 0; m < S::M; ++m) cface[f][b][m] = static_cast<T>(S::tab.cface[f][b][m]);
@@ -259,19 +258,9 @@ template <int D, int K, int SP, typename T> struct RtTab {
       }
     for (int p = 0; p < S::NS; ++p)
       for (int m = 0; m < S::M; ++m) phi_s[p][m] = static_cast<T>(S::tab.phi_s[p][m]);
-    // face point b: tangential Gauss indices, lower direction fastest (as in
-    // Space::Tables); tangential mode t likewise
     for (int b = 0; b < S::NFP; ++b)
       for (int t = 0; t < TM; ++t) {
-        double v = 1.0;
-        int rb = b, rt = t;
-        for (int j = 0; j < D - 1; ++j) {
-          v *= leg(rt % (K + 1), S::gx(rb % S::NG));
-          rb /= S::NG;
-          rt /= (K + 1);
-        }
-        ftan[b][t] = static_cast<T>(v);
-        wftan[b][t] = static_cast<T>(S::tab.wb[b] * v);
+        ftan[b][t] = static_cast<T>(S::tab.ftan[b][t]);
       }
   }
 };
@@ -299,7 +288,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
   static constexpr bool BIG = (M * V > 100);
   static constexpr int UQ = BIG ? 1 : S::NQ;    // unroll of volume-point loops
   static constexpr int US = BIG ? 1 : NS;       // unroll of S_K loops
-  static constexpr int TM = ipow(K + 1, D - 1);
+  static constexpr int TM = S::TM;
   using RT = Rt<D, K, SP, T>;
 
   struct State {
@@ -480,27 +469,6 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
       u[v] = a;
     }
   }
-  // r -= scale / dx_d * (face integral of fn phi_m) for face f, from
-  // H[v][t] = sum_b wb phi_t(b) fn_v(b) and h0[v] = sum_b wb fn_v(b):
-  // phi_m = P_{e_d}(side) phi_t on the face.
-  __device__ __forceinline__ static void face_scatter(int f, const T (&H)[V][TM], const double* h0,
-                                                      const InstDev& I, double scale, Acc& r) {
-    const int d = f / 2;
-    const bool up = (f & 1) != 0;
-    const double sc = scale * I.rdx[d];
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-      r.a0[v] = fma(up ? -sc : sc, h0[v], r.a0[v]);
-#pragma unroll
-      for (int m = 1; m < M; ++m) {
-        const int e = S::modes.e[m][d];
-        // outward normal sign times P_e(side): side^(e + 1)
-        const bool plus = up || ((e + 1) % 2 == 0);
-        const T c = T((plus ? -sc : sc) * S::pfac(m));
-        r.ah[v][m - 1] = fma(c, H[v][tmode(m, d)], r.ah[v][m - 1]);
-      }
-    }
-  }
   // r -= scale / dx_d * cface[f][b][m] fn(b) for one face point b of face f
   __device__ __forceinline__ static void face_point_scatter(int f, int b, const T* fn, const InstDev& I,
                                                             double scale, Acc& r) {
@@ -514,15 +482,6 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
       for (int m = 1; m < M; ++m) r.ah[v][m - 1] = fma(RT::tab.cface[f][b][m], g, r.ah[v][m - 1]);
     }
   }
-  __device__ __forceinline__ static void face_gather(const T* fn, int b, T (&H)[V][TM], double* h0) {
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-      h0[v] = fma(S::tab.wb[b], static_cast<double>(fn[v]), h0[v]);
-#pragma unroll
-      for (int t = 0; t < TM; ++t) H[v][t] = fma(RT::tab.wftan[b][t], fn[v], H[v][t]);
-    }
-  }
-
   __device__ __forceinline__ static void op_local_big(const State& s, const InstDev& I, double scale,
                                                       Acc& r) {
     volume(s, I, scale, r);
@@ -1077,11 +1036,18 @@ __device__ __forceinline__ void stage_local_item(const KArgs& a, const BlockItem
   raise_flag(&ctl->flags, nonfin, CRKDG_F_NONFINITE);
 }
 
-// The stage kernels walk the tiles of their block map with a grid stride: a
-// grid of one workgroup per tile, or a persistent grid (a multiple of 8, so
-// that a workgroup stays on one XCD's run of tiles).
+// Each stage kernel comes in two forms: one workgroup per tile of the block
+// map, and a persistent grid (a multiple of 8, so that a workgroup stays on
+// one XCD's run of tiles) walking the map with a grid stride.  The loop of
+// the persistent form costs registers and scheduling freedom (measured: the
+// 2D Q^2 final stage runs 2x slower as a loop even with one tile per
+// workgroup), so the one-tile form serves grids of one workgroup per tile.
 template <int D, int K, int SP, int SYS, typename T>
 __global__ __launch_bounds__(BLOCK) void k_stage_local(KArgs a) {
+  if (static_cast<int>(blockIdx.x) < a.n_items) stage_local_item<D, K, SP, SYS, T>(a, a.bmap[blockIdx.x]);
+}
+template <int D, int K, int SP, int SYS, typename T>
+__global__ __launch_bounds__(BLOCK) void k_stage_local_p(KArgs a) {
   for (int it = blockIdx.x; it < a.n_items; it += gridDim.x) stage_local_item<D, K, SP, SYS, T>(a, a.bmap[it]);
 }
 
@@ -1160,6 +1126,10 @@ __device__ __forceinline__ void stage_final_item(const KArgs& a, const BlockItem
 
 template <int D, int K, int SP, int SYS, typename T>
 __global__ __launch_bounds__(BLOCK) void k_stage_final(KArgs a) {
+  if (static_cast<int>(blockIdx.x) < a.n_items) stage_final_item<D, K, SP, SYS, T>(a, a.bmap[blockIdx.x]);
+}
+template <int D, int K, int SP, int SYS, typename T>
+__global__ __launch_bounds__(BLOCK) void k_stage_final_p(KArgs a) {
   for (int it = blockIdx.x; it < a.n_items; it += gridDim.x) stage_final_item<D, K, SP, SYS, T>(a, a.bmap[it]);
 }
 

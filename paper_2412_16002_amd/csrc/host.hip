@@ -772,13 +772,14 @@ static int launch_stage(crkdg_mesh* m, int gi, int stage, const Slots& slots, cr
   // the queue holds a few percent of the cells: up to 256 workgroups drain it
   const int qblocks = static_cast<int>(std::min<int64_t>(256, (g.ncells + BLOCK - 1) / BLOCK));
   const int grid = stage_grid(g);
+  const bool persistent = grid < g.n_items;
   if (stage <= g.stages) {
     a.a = bt.a[stage];
-    g.ops->stage_local(a, grid, g.tune.threads, s);
+    (persistent ? g.ops->stage_local_p : g.ops->stage_local)(a, grid, g.tune.threads, s);
     g.ops->queue_local(a, qblocks, BLOCK, s);
   } else {
     for (int j = 0; j < 4; ++j) a.b[j] = bt.b[j];
-    g.ops->stage_final(a, grid, g.tune.threads, s);
+    (persistent ? g.ops->stage_final_p : g.ops->stage_final)(a, grid, g.tune.threads, s);
     g.ops->queue_final(a, qblocks, BLOCK, s);
   }
   return CRKDG_OK;

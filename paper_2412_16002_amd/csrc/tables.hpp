@@ -87,6 +87,7 @@ template <int D, int K, int SP> struct Space {
   static constexpr int NFP = (D == 1) ? 1 : ipow(NG, D - 1);  // points per face
   static constexpr int NL = (K == 1) ? 2 : 3;        // Lobatto points in S_K
   static constexpr int NS_RAW = D * ipow(NG, D - 1) * NL;
+  static constexpr int TM = ipow(K + 1, D - 1);      // tangential modes of a face
 
   static constexpr double gx(int i) { return Gauss<NG>::x[i]; }
   static constexpr double gw(int i) { return Gauss<NG>::w[i]; }
@@ -148,10 +149,12 @@ template <int D, int K, int SP> struct Space {
     double phi_f[NF][NFP][M];
     double cface[NF][NFP][M];  // pfac * side * wb * phi: face residual coefficients
     double wb[NFP];         // face weights (sum 1)
+    double ftan[NFP][TM];   // tangential Legendre products at the face points
     double xs[NS_RAW][3];   // S_K points (first NS entries valid)
     double phi_s[NS_RAW][M];
     int ns;
-    constexpr Tables() : xq{}, wq{}, phi_v{}, cvol{}, xf{}, phi_f{}, cface{}, wb{}, xs{}, phi_s{}, ns(0) {
+    constexpr Tables()
+        : xq{}, wq{}, phi_v{}, cvol{}, xf{}, phi_f{}, cface{}, wb{}, ftan{}, xs{}, phi_s{}, ns(0) {
       for (int q = 0; q < NQ; ++q) {
         int r = q;
         double w = 1.0;
@@ -178,6 +181,18 @@ template <int D, int K, int SP> struct Space {
           r /= NG;
         }
         wb[b] = w;
+        // face point b and tangential mode t: indices over the directions
+        // other than the normal, lower direction fastest
+        for (int t = 0; t < TM; ++t) {
+          double v = 1.0;
+          int rb = b, rt = t;
+          for (int j = 0; j < D - 1; ++j) {
+            v *= leg(rt % (K + 1), gx(rb % NG));
+            rb /= NG;
+            rt /= (K + 1);
+          }
+          ftan[b][t] = v;
+        }
       }
       for (int f = 0; f < NF; ++f) {
         const int d = f / 2;
