@@ -62,17 +62,26 @@ struct BlockItem {
 constexpr int TILE_X = 32;
 constexpr int TILE_SHIFT = 5;   // log2 TILE_X
 
+// a thread's cell: natural index and coordinates
+struct CellPos {
+  int64_t c;
+  int32_t x, y, z;
+};
+
 __device__ __forceinline__ int64_t tile_cell(const BlockItem& bi, int dim, const int32_t* n,
-                                             int64_t ncell, int shift, bool& active) {
+                                             int64_t ncell, int shift, bool& active, CellPos* pos = nullptr) {
   if (dim == 1) {
     const int64_t c = static_cast<int64_t>(bi.x0) + threadIdx.x;
     active = c < ncell;
+    if (pos) *pos = CellPos{c, static_cast<int32_t>(c), 0, 0};
     return c;
   }
   const int x = bi.x0 + static_cast<int>(threadIdx.x & ((1u << shift) - 1u));
   const int y = bi.y0 + static_cast<int>(threadIdx.x >> shift);
   active = x < n[0] && y < n[1];
-  return x + static_cast<int64_t>(n[0]) * (y + static_cast<int64_t>(n[1]) * bi.z);
+  const int64_t c = x + static_cast<int64_t>(n[0]) * (y + static_cast<int64_t>(n[1]) * bi.z);
+  if (pos) *pos = CellPos{c, x, y, bi.z};
+  return c;
 }
 
 struct Slots {
@@ -501,13 +510,14 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
   }
 
   __device__ __forceinline__ static void op_dg_big(const State& s, const double* avg, const T* hi,
-                                                   int64_t c, const InstDev& I, double scale, Acc& r) {
+                                                   const CellPos& p, const InstDev& I, double scale, Acc& r) {
+    const int64_t c = p.c;
     volume(s, I, scale, r);
     static_for<S::NF>([&](auto F) {
       constexpr int f = decltype(F)::value;
       constexpr int d = f / 2;
       constexpr bool upper = (f & 1) != 0;   // this cell is the lower cell of the face
-      const int64_t nb = neighbour(c, f, I);
+      const int64_t nb = neighbour(p, f, I);
       T Ri[V][TM], Re[V][TM];
       face_modes_mem(avg, hi, I.ncell, c, f, Ri);
       if (nb >= 0) {
@@ -576,45 +586,54 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
     }
   }
 
-  // neighbour across face f of cell c (-1 on an outflow boundary)
-  __device__ __forceinline__ static int64_t neighbour(int64_t c, int f, const InstDev& I) {
+  // neighbour across face f of the cell at p (-1 on an outflow boundary);
+  // from the coordinates, without integer division
+  __device__ __forceinline__ static int64_t neighbour(const CellPos& p, int f, const InstDev& I) {
     const int d = f / 2;
-    const int side = (f & 1) ? 1 : -1;
-    int64_t stride = 1;
-#pragma unroll
-    for (int j = 0; j < 3; ++j)
-      if (j < d) stride *= I.n[j];
-    const int64_t i = (c / stride) % I.n[d];
-    int64_t ni = i + side;
-    if (ni < 0 || ni >= I.n[d]) {
-      if (I.bc[d] != CRKDG_BC_PERIODIC) return -1;
-      ni = (ni < 0) ? ni + I.n[d] : ni - I.n[d];
+    const int q = (d == 0) ? p.x : (d == 1) ? p.y : p.z;
+    const int64_t stride = (d == 0) ? 1 : (d == 1) ? static_cast<int64_t>(I.n[0])
+                                                   : static_cast<int64_t>(I.n[0]) * I.n[1];
+    const int nd = I.n[d];
+    const bool periodic = I.bc[d] == CRKDG_BC_PERIODIC;
+    if ((f & 1) == 0) {
+      if (q > 0) return p.c - stride;
+      return periodic ? p.c + (nd - 1) * stride : -1;
     }
-    return c + (ni - i) * stride;
+    if (q < nd - 1) return p.c + stride;
+    return periodic ? p.c - (nd - 1) * stride : -1;
   }
+
 
   // F = -div^DG f with the Lax--Friedrichs flux (Sec. 2.1).  Each face flux is
   // formed in the canonical (lower cell, upper cell) orientation with the same
   // operation order in both cells, so the two cells of a face see bitwise the
   // same value and the averages are updated conservatively.
   __device__ __forceinline__ static void op_dg(const State& s, const double* avg, const T* hi,
-                                               int64_t c, const InstDev& I, double scale, Acc& r) {
+                                               const CellPos& p, const InstDev& I, double scale, Acc& r) {
     if constexpr (BIG) {
-      op_dg_big(s, avg, hi, c, I, scale, r);
-      return;
+      op_dg_big(s, avg, hi, p, I, scale, r);
+    } else {
+      op_dg_from(s, p, I, scale, r,
+                 [&](int, int64_t nb, State& sn) { load(avg, hi, I.ncell, nb, sn); });
     }
+  }
+
+  // F with the neighbour states read by getnb(f, nb, state)
+  template <class GetNb>
+  __device__ __forceinline__ static void op_dg_from(const State& s, const CellPos& p, const InstDev& I,
+                                                    double scale, Acc& r, GetNb getnb) {
     volume(s, I, scale, r);
 #pragma unroll
     for (int f = 0; f < S::NF; ++f) {
       const int d = f / 2;
       const bool upper = (f & 1) != 0;   // this cell is the lower cell of the face
-      const int64_t nb = neighbour(c, f, I);
+      const int64_t nb = neighbour(p, f, I);
       T ui[S::NFP][V], ue[S::NFP][V];
 #pragma unroll
       for (int b = 0; b < S::NFP; ++b) at_face(s, f, b, ui[b]);
       if (nb >= 0) {
         State sn;
-        load(avg, hi, I.ncell, nb, sn);
+        getnb(f, nb, sn);
 #pragma unroll
         for (int b = 0; b < S::NFP; ++b) at_face(sn, f ^ 1, b, ue[b]);
       } else {
@@ -1071,7 +1090,8 @@ __device__ __forceinline__ void stage_final_item(const KArgs& a, const BlockItem
   T* o_hi = hi_ptr<T>(sel_hi(a.slots, sl_out), I.hi_off);
 
   bool active;
-  const int64_t c = tile_cell(bi, D, I.n, I.ncell, a.tile_shift, active);
+  CellPos pos;
+  const int64_t c = tile_cell(bi, D, I.n, I.ncell, a.tile_shift, active, &pos);
   bool bad = false, nonfin = false;
   double a0[D];
 #pragma unroll
@@ -1088,7 +1108,7 @@ __device__ __forceinline__ void stage_final_item(const KArgs& a, const BlockItem
       const T* j_hi = hi_ptr<T>(sel_hi(a.slots, sl), I.hi_off);
       typename C::State uj;
       C::load(j_avg, j_hi, I.ncell, c, uj);
-      C::op_dg(uj, j_avg, j_hi, c, I, dt * a.b[j - 1], r);
+      C::op_dg(uj, j_avg, j_hi, pos, I, dt * a.b[j - 1], r);
     }
     typename C::State base;
     C::load(b_avg, b_hi, I.ncell, c, base);
