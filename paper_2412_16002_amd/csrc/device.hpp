@@ -519,7 +519,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
       constexpr bool upper = (f & 1) != 0;   // this cell is the lower cell of the face
       const int64_t nb = neighbour(p, f, I);
       T Ri[V][TM], Re[V][TM];
-      face_modes_mem(avg, hi, I.ncell, c, f, Ri);
+      face_modes_state(s, f, Ri);
       if (nb >= 0) {
         face_modes_mem(avg, hi, I.ncell, nb, f ^ 1, Re);
       } else {
