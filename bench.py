@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--workloads", default="euler3d,batched",
                     help="extra workloads to measure (comma list of euler3d, batched; empty for none)")
+    ap.add_argument("--only", choices=["euler3d", "batched"], default=None,
+                    help="run only this extra workload and print its results (for profiling)")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (to scale HBM byte counters)")
@@ -331,6 +333,9 @@ def main():
         print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "launches": 3}), flush=True)
         return
     stream = torch.cuda.current_stream()
+    if args.only:
+        print(json.dumps({args.only: extra_workload(args.only, args, crkdg, inputs, torch, stream)}), flush=True)
+        return
     Nc = args.n * args.n
     M, V, s = 9, 4, 3
     dof = Nc * M * V
