@@ -67,6 +67,10 @@ extern "C" {
 #define CRKDG_SPACE_Q 0 /* degree <= k in each variable (1D: P^k) */
 #define CRKDG_SPACE_P 1 /* total degree <= k */
 
+#define CRKDG_SCHEME_CRKDG 0 /* inner stages with the local operator G (Sec. 3.1, Scheme 1L of App. B) */
+#define CRKDG_SCHEME_RKDG 1  /* standard RKDG (Sec. 2.1): F in every stage, same Butcher table,
+                                limiter and check after every stage */
+
 #define CRKDG_FP64 0  /* every mode and all arithmetic in FP64 */
 #define CRKDG_MIXED 1 /* modes >= 1 and transforms/fluxes in FP32; averages,
                          admissibility checks, limiter theta and the
@@ -107,6 +111,7 @@ typedef struct crkdg_problem {
   int32_t limiter;   /* 1: scaling limiter after every stage; 0: off */
   double cfl;        /* trial step dt = cfl / sum_d (a0_d / dx_d)   (Sec. 4.1) */
   int32_t max_halvings; /* bound on halvings within one step (Sec. 4.1) */
+  int32_t scheme;    /* CRKDG_SCHEME_* (0, the cRKDG scheme, in a zeroed struct) */
 } crkdg_problem;
 
 typedef struct crkdg_mesh crkdg_mesh; /* opaque handle */
@@ -278,7 +283,7 @@ typedef struct crkdg_tuning {
   int32_t grid;      /* 0: one workgroup per tile; else a multiple of 8 */
   int32_t dim, k, space, stages, n_inst; /* read only: the group */
   int32_t n_items;   /* read only: tiles in the group's map */
-  int32_t pad;
+  int32_t scheme;    /* read only: CRKDG_SCHEME_* of the group */
   int64_t n_cells;   /* read only: cells of the group */
   double ms;         /* read only: stage time of one attempt measured by crkdg_autotune */
 } crkdg_tuning;

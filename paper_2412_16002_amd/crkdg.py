@@ -21,6 +21,7 @@ BC_PERIODIC, BC_OUTFLOW = 0, 1
 SYS_ADVECTION, SYS_BURGERS, SYS_EULER = 0, 1, 2
 SPACE_Q, SPACE_P = 0, 1
 FP64, MIXED = 0, 1
+SCHEME_CRKDG, SCHEME_RKDG = 0, 1
 E_ARG, E_HIP, E_UNSUPPORTED, E_LAYOUT = -1, -2, -3, -4
 S_REJECTED, S_DT_UNDERFLOW, S_NONFINITE, S_DONE = 1, 2, 3, 4
 F_AVERAGE, F_NONFINITE = 1, 2
@@ -34,6 +35,7 @@ class CProblem(C.Structure):
         ("bound_lo", C.c_double), ("bound_hi", C.c_double), ("eps", C.c_double),
         ("k", C.c_int32), ("space", C.c_int32), ("stages", C.c_int32), ("precision", C.c_int32),
         ("limiter", C.c_int32), ("cfl", C.c_double), ("max_halvings", C.c_int32),
+        ("scheme", C.c_int32),
     ]
 
 
@@ -71,7 +73,7 @@ class CStepInfo(C.Structure):
 class CTuning(C.Structure):
     _fields_ = [("threads", C.c_int32), ("tile_x", C.c_int32), ("grid", C.c_int32), ("dim", C.c_int32),
                 ("k", C.c_int32), ("space", C.c_int32), ("stages", C.c_int32), ("n_inst", C.c_int32),
-                ("n_items", C.c_int32), ("pad", C.c_int32), ("n_cells", C.c_int64), ("ms", C.c_double)]
+                ("n_items", C.c_int32), ("scheme", C.c_int32), ("n_cells", C.c_int64), ("ms", C.c_double)]
 
 
 def _load():
@@ -154,6 +156,7 @@ class Problem:
     limiter: int = 1
     cfl: float = 0.1
     max_halvings: int = 40
+    scheme: int = SCHEME_CRKDG
 
     def to_c(self) -> CProblem:
         p = CProblem()
@@ -167,18 +170,19 @@ class Problem:
         p.system, p.k, p.space, p.stages = self.system, self.k, self.space, self.stages
         p.precision, p.limiter, p.max_halvings = self.precision, int(self.limiter), self.max_halvings
         p.gamma, p.bound_lo, p.bound_hi = self.gamma, self.bound_lo, self.bound_hi
-        p.eps, p.cfl = self.eps, self.cfl
+        p.eps, p.cfl, p.scheme = self.eps, self.cfl, self.scheme
         return p
 
 
 _SYS_NAMES = {"advection": SYS_ADVECTION, "burgers": SYS_BURGERS, "euler": SYS_EULER}
 _BC_NAMES = {"periodic": BC_PERIODIC, "outflow": BC_OUTFLOW}
+_SCHEME_NAMES = {"crkdg": SCHEME_CRKDG, "rkdg": SCHEME_RKDG}
 
 
 def problem_from_params(params: dict) -> Problem:
     """Problem from a workload parameter dict (names as in crkdg_problem,
     enumerations spelled as words: system 'euler', space 'Q', bc 'periodic',
-    precision 'fp64' / 'mixed')."""
+    precision 'fp64' / 'mixed', scheme 'crkdg' / 'rkdg')."""
     d = params["dim"]
     bc = tuple(_BC_NAMES[b] for b in params.get("bc", ("periodic",) * d)) + (BC_PERIODIC,) * (3 - d)
     n = tuple(params["n"]) + (1,) * (3 - d)
@@ -190,7 +194,8 @@ def problem_from_params(params: dict) -> Problem:
         bc=bc, vel=tuple(params.get("vel", (1.0, 1.0, 1.0))), gamma=params.get("gamma", 1.4),
         bound_lo=params.get("bound_lo", -math.inf), bound_hi=params.get("bound_hi", math.inf),
         eps=params.get("eps", 1e-8), limiter=int(params.get("limiter", True)),
-        cfl=params.get("cfl", 0.1), max_halvings=params.get("max_halvings", 40))
+        cfl=params.get("cfl", 0.1), max_halvings=params.get("max_halvings", 40),
+        scheme=_SCHEME_NAMES[params.get("scheme", "crkdg")])
 
 
 class State:

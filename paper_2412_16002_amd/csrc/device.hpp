@@ -1012,8 +1012,10 @@ __device__ __forceinline__ T* hi_ptr(void* p, int64_t off) {
 }
 
 // Inner stage i = 2..s (Scheme 1L): out = L(base + dt a G(in)); flags on a
-// non-admissible unlimited average.
-template <int D, int K, int SP, int SYS, typename T>
+// non-admissible unlimited average.  With DG the operator is F instead of G:
+// the inner stage of the standard RKDG scheme (Sec. 2.1) with the same
+// Butcher table, limiter and check, which needs the neighbours' traces.
+template <int D, int K, int SP, int SYS, typename T, bool DG = false>
 __device__ __forceinline__ void stage_local_item(const KArgs& a, const BlockItem& bi) {
   using C = Cell<D, K, SP, SYS, T>;
   if (bi.inst < 0) return;  // padding entry of the XCD-ordered block map
@@ -1034,14 +1036,18 @@ __device__ __forceinline__ void stage_local_item(const KArgs& a, const BlockItem
   const double dt = ctl->dt;
 
   bool active;
-  const int64_t c = tile_cell(bi, D, I.n, I.ncell, a.tile_shift, active);
+  CellPos pos;
+  const int64_t c = tile_cell(bi, D, I.n, I.ncell, a.tile_shift, active, DG ? &pos : nullptr);
   bool bad = false, nonfin = false;
   if (active) {
     typename C::State u;
     C::load(in_avg, in_hi, I.ncell, c, u);
     typename C::Acc r;
     C::zero(r);
-    C::op_local(u, I, dt * a.a, r);
+    if constexpr (DG)
+      C::op_dg(u, in_avg, in_hi, pos, I, dt * a.a, r);
+    else
+      C::op_local(u, I, dt * a.a, r);
     typename C::State base, out;
     C::load(b_avg, b_hi, I.ncell, c, base);
     C::combine(base, r, out);
@@ -1068,6 +1074,15 @@ __global__ __launch_bounds__(BLOCK) void k_stage_local(KArgs a) {
 template <int D, int K, int SP, int SYS, typename T>
 __global__ __launch_bounds__(BLOCK) void k_stage_local_p(KArgs a) {
   for (int it = blockIdx.x; it < a.n_items; it += gridDim.x) stage_local_item<D, K, SP, SYS, T>(a, a.bmap[it]);
+}
+// inner stage of the standard RKDG scheme (operator F)
+template <int D, int K, int SP, int SYS, typename T>
+__global__ __launch_bounds__(BLOCK) void k_stage_inner_dg(KArgs a) {
+  if (static_cast<int>(blockIdx.x) < a.n_items) stage_local_item<D, K, SP, SYS, T, true>(a, a.bmap[blockIdx.x]);
+}
+template <int D, int K, int SP, int SYS, typename T>
+__global__ __launch_bounds__(BLOCK) void k_stage_inner_dg_p(KArgs a) {
+  for (int it = blockIdx.x; it < a.n_items; it += gridDim.x) stage_local_item<D, K, SP, SYS, T, true>(a, a.bmap[it]);
 }
 
 // Final stage (Scheme 1L): out = L(base + dt sum_j b_j F(u~^(j))); also the

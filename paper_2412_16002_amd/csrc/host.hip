@@ -81,6 +81,7 @@ struct Tune {
 struct Group {
   const VariantOps* ops;
   int stages;
+  int scheme;                   // CRKDG_SCHEME_*: operator of the inner stages
   int dim;
   std::vector<int> insts;
   int nblocks = 0;              // default map: grid size (a multiple of 8, padded)
@@ -188,6 +189,7 @@ int validate(const crkdg_problem& p, int idx) {
   if (p.system != CRKDG_SYS_EULER && !(p.bound_lo <= p.bound_hi)) return bad("bound_lo > bound_hi");
   if (!(p.cfl > 0.0)) return bad("cfl must be positive");
   if (p.max_halvings < 0) return bad("max_halvings must be >= 0");
+  if (p.scheme != CRKDG_SCHEME_CRKDG && p.scheme != CRKDG_SCHEME_RKDG) return bad("unknown scheme");
   int64_t nc = 1;
   for (int d = 0; d < p.dim; ++d) nc *= p.n[d];
   if (nc > INT32_MAX) return bad("more than 2^31 - 1 cells in one instance");
@@ -411,7 +413,7 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
     delete m;
     return fail(CRKDG_E_HIP, "hipGetDevice failed");
   }
-  std::map<std::tuple<const VariantOps*, int>, int> gidx;
+  std::map<std::tuple<const VariantOps*, int, int>, int> gidx;
   int64_t avg_off = 0, hi_off = 0;
   m->inst.resize(n_inst);
   m->lay.resize(n_inst);
@@ -471,7 +473,7 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
     I.cfl = p.cfl;
     m->max_stages = std::max(m->max_stages, p.stages);
 
-    auto key = std::make_tuple(ops, p.stages);
+    auto key = std::make_tuple(ops, p.stages, p.scheme);
     auto it = gidx.find(key);
     int g;
     if (it == gidx.end()) {
@@ -480,6 +482,7 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
       Group G;
       G.ops = ops;
       G.stages = p.stages;
+      G.scheme = p.scheme;
       m->groups.push_back(G);
       logical.emplace_back();
     } else {
@@ -775,7 +778,10 @@ static int launch_stage(crkdg_mesh* m, int gi, int stage, const Slots& slots, cr
   const bool persistent = grid < g.n_items;
   if (stage <= g.stages) {
     a.a = bt.a[stage];
-    (persistent ? g.ops->stage_local_p : g.ops->stage_local)(a, grid, g.tune.threads, s);
+    if (g.scheme == CRKDG_SCHEME_RKDG)
+      (persistent ? g.ops->stage_inner_dg_p : g.ops->stage_inner_dg)(a, grid, g.tune.threads, s);
+    else
+      (persistent ? g.ops->stage_local_p : g.ops->stage_local)(a, grid, g.tune.threads, s);
     g.ops->queue_local(a, qblocks, BLOCK, s);
   } else {
     for (int j = 0; j < 4; ++j) a.b[j] = bt.b[j];
@@ -902,6 +908,7 @@ void tune_out(const Group& g, crkdg_tuning* o) {
   o->k = g.ops->k;
   o->space = g.ops->space;
   o->stages = g.stages;
+  o->scheme = g.scheme;
   o->n_inst = static_cast<int32_t>(g.insts.size());
   o->n_items = g.n_items;
   o->n_cells = g.ncells;

@@ -15,6 +15,7 @@ struct VariantOps {
   int rec_bytes;   // bytes of one deferred-limiter queue record
   Launch stage_local, stage_final, limit, cfl, project, queue_local, queue_final;
   Launch stage_local_p, stage_final_p;   // persistent-grid forms
+  Launch stage_inner_dg, stage_inner_dg_p; // inner stage with F (standard RKDG)
 };
 
 template <int D, int K, int SP, int SYS, typename T> struct Ops {
@@ -30,6 +31,12 @@ template <int D, int K, int SP, int SYS, typename T> struct Ops {
   }
   static void stage_final_p(const KArgs& a, int nb, int nt, hipStream_t s) {
     hipLaunchKernelGGL((k_stage_final_p<D, K, SP, SYS, T>), dim3(nb), dim3(nt), 0, s, a);
+  }
+  static void stage_inner_dg(const KArgs& a, int nb, int nt, hipStream_t s) {
+    hipLaunchKernelGGL((k_stage_inner_dg<D, K, SP, SYS, T>), dim3(nb), dim3(nt), 0, s, a);
+  }
+  static void stage_inner_dg_p(const KArgs& a, int nb, int nt, hipStream_t s) {
+    hipLaunchKernelGGL((k_stage_inner_dg_p<D, K, SP, SYS, T>), dim3(nb), dim3(nt), 0, s, a);
   }
   static void limit(const KArgs& a, int nb, int nt, hipStream_t s) {
     hipLaunchKernelGGL((k_limit<D, K, SP, SYS, T>), dim3(nb), dim3(nt), 0, s, a);
@@ -50,7 +57,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Ops {
     return VariantOps{D, K, SP, SYS, sizeof(T) == 8 ? CRKDG_FP64 : CRKDG_MIXED,
                       C::M, C::V, C::S::NQ, C::NS, static_cast<int>(sizeof(typename C::Record)),
                       &stage_local, &stage_final, &limit, &cfl, &project, &queue_local, &queue_final,
-                      &stage_local_p, &stage_final_p};
+                      &stage_local_p, &stage_final_p, &stage_inner_dg, &stage_inner_dg_p};
   }
 };
 

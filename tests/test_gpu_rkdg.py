@@ -1,0 +1,189 @@
+"""The standard RKDG scheme (Sec. 2.1: the operator F in every stage, with
+the Butcher tables, limiter and admissibility check of the cRKDG schemes) on
+the GPU against the oracle's standard-RKDG path, and what separates the two
+schemes: the inner stages of RKDG read the neighbours, those of cRKDG do
+not; their final stages are the same operation."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from _helpers import gpu_problem, oracle_problem, parity_tolerance, random_state, rel_err_per_var, round_hi
+from test_gpu_parity import CASES, FP64_TOL
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2412_16002_amd import crkdg
+    return crkdg
+
+
+def _setup(lib, name, precision="fp64", scheme="rkdg"):
+    params = dict(CASES[name], precision=precision, scheme=scheme)
+    return params, oracle.CRKDG(oracle_problem(params)), lib.Mesh(gpu_problem(params))
+
+
+def _states(mesh, coeffs):
+    out = []
+    for c in coeffs:
+        st = mesh.new_state()
+        mesh.set_legendre(st, c)
+        out.append(st)
+    return out
+
+
+STAGE_CASES = ["burgers1d_p2", "euler1d_p3_outflow", "euler1d_p1", "euler2d_q2", "euler2d_q1_outflow",
+               "euler2d_q3", "euler2d_p3", "adv2d_q2", "euler3d_q1", "adv3d_q2", "euler3d_q2"]
+
+
+@pytest.mark.parametrize("name", STAGE_CASES)
+def test_rkdg_stage_parity(lib, name):
+    """Every stage of standard RKDG from the same random limited states:
+    inner stages u~^n + dt a F(u~^(i-1)), then the final stage, each limited."""
+    params, o, mesh = _setup(lib, name)
+    s = o.p.stages
+    tilde = [random_state(o, seed=60 + j, rel_amp=0.1) for j in range(s)]
+    U = [o.from_legendre(c) for c in tilde]
+    dt = 0.8 * o.trial_dt(U[0])
+    states = _states(mesh, tilde)
+    out = mesh.new_state()
+    ctl = mesh.new_ctl()
+    for i in range(2, s + 2):
+        _say(f"[rkdg stage] {name} stage {i}")
+        ref_u = o.stage(i, U[0], U, dt, op=o.F)
+        ok_ref = bool(np.all(o.admissible_average(o.cell_average(ref_u))))
+        ref = o.to_legendre(o.limit(ref_u)[0])
+        mesh.ctl_write(ctl, [{"dt": dt}])
+        mesh.stage(i, states, out, ctl)
+        got = mesh.get_legendre(out)
+        c = mesh.ctl_read(ctl)[0]
+        err = float(np.max(np.abs(got - ref) / parity_tolerance(o, o.to_legendre(ref_u), ref, FP64_TOL)))
+        _say(f"   error/tolerance {err:.2e} flags {c['flags']} oracle-admissible {ok_ref}")
+        assert (c["flags"] == 0) == ok_ref
+        assert err < 1.0
+
+
+@pytest.mark.parametrize("name", ["burgers1d_p2", "euler1d_p3_outflow", "euler2d_q2", "euler2d_p3", "adv2d_q2",
+                                  "euler3d_q1", "euler3d_q2"])
+def test_rkdg_step_parity(lib, name):
+    """Three accepted standard-RKDG steps through the device controller
+    against the oracle's steps with the F operator in every stage."""
+    params, o, mesh = _setup(lib, name)
+    C0 = random_state(o, seed=71, rel_amp=0.1)
+    slots = mesh.new_slots()
+    mesh.set_legendre(slots[0], C0)
+    ctl = mesh.new_ctl()
+    mesh.start(slots, ctl, t0=0.0)
+    U = o.from_legendre(C0)
+    t = 0.0
+    for n in range(3):
+        _say(f"[rkdg step] {name} step {n}")
+        U, info_o = o.step(U, t, op=o.F)
+        t = info_o["t"]
+        info = mesh.step(slots, ctl)[0]
+        assert info["status"] == 0 and info["halvings"] == info_o["halvings"]
+        assert math.isclose(info["dt"], info_o["dt"], rel_tol=1e-12)
+        got = mesh.get_legendre(slots[info["cur"]])
+        err = rel_err_per_var(got, o.to_legendre(U))
+        _say(f"   dt {info['dt']:.4e} rel err {err:.2e}")
+        assert err < 10 * FP64_TOL
+
+
+@pytest.mark.parametrize("name", ["euler2d_q2", "euler2d_p3", "euler3d_q2"])
+def test_rkdg_mixed_stage_parity(lib, name):
+    """Mixed precision, standard RKDG: each stage within 1e-5 of the
+    variable's magnitude (averages 1e-6) of the FP64 oracle; limited points
+    in the admissible set."""
+    params, o, mesh = _setup(lib, name, precision="mixed")
+    s = o.p.stages
+    tilde = [round_hi(random_state(o, seed=80 + j, rel_amp=0.1), "mixed") for j in range(s)]
+    U = [o.from_legendre(c) for c in tilde]
+    dt = 0.8 * o.trial_dt(U[0])
+    states = _states(mesh, tilde)
+    out = mesh.new_state()
+    ctl = mesh.new_ctl()
+    for i in range(2, s + 2):
+        _say(f"[rkdg mixed stage] {name} stage {i}")
+        ref = o.to_legendre(o.limit(o.stage(i, U[0], U, dt, op=o.F))[0])
+        mesh.ctl_write(ctl, [{"dt": dt}])
+        mesh.stage(i, states, out, ctl)
+        got = mesh.get_legendre(out)
+        err, err0 = rel_err_per_var(got, ref), rel_err_per_var(got[:, :, :1], ref[:, :, :1])
+        _say(f"   rel err {err:.2e} (averages {err0:.2e})")
+        assert err < 1e-5 and err0 < 1e-6
+        assert o.bound_violations(o.from_legendre(got)) == 0
+
+
+@pytest.mark.parametrize("name", ["euler2d_q2", "euler3d_q1"])
+def test_inner_stage_locality(lib, name):
+    """Perturbing one cell changes the cRKDG inner stage in that cell only
+    (G is element-local, Sec. 3.1), and the RKDG inner stage also in the
+    cells that share a face with it; the final stages of the two schemes
+    are bitwise the same operation."""
+    C = {}
+    for scheme in ("crkdg", "rkdg"):
+        params, o, mesh = _setup(lib, name, scheme=scheme)
+        base = random_state(o, seed=90, rel_amp=0.1)
+        pert = base.copy()
+        c0 = o.ncell // 2
+        pert[c0, :, 1:] *= 0.5
+        outs = []
+        for tilde in (base, pert):
+            states = _states(mesh, [tilde] * o.p.stages)
+            out = mesh.new_state()
+            ctl = mesh.new_ctl()
+            mesh.ctl_write(ctl, [{"dt": 0.5 * o.trial_dt(o.from_legendre(base))}])
+            mesh.stage(2, states, out, ctl)
+            inner = mesh.get_legendre(out)
+            mesh.ctl_write(ctl, [{"dt": 0.5 * o.trial_dt(o.from_legendre(base))}])
+            mesh.stage(o.p.stages + 1, states, out, ctl)
+            outs.append((inner, mesh.get_legendre(out)))
+        changed = np.flatnonzero(np.any(outs[0][0] != outs[1][0], axis=(1, 2)))
+        _say(f"[locality] {name} {scheme}: cells changed by the inner stage {changed.tolist()}")
+        if scheme == "crkdg":
+            assert changed.tolist() == [c0]
+        else:
+            assert c0 in changed and len(changed) == 1 + 2 * o.d
+        C[scheme] = outs
+    for j in range(2):
+        assert np.array_equal(C["crkdg"][j][1], C["rkdg"][j][1])
+
+
+def test_mixed_batch_of_both_schemes(lib):
+    """A batch holding the same problem under both schemes gets one kernel
+    group per scheme, and each instance steps bitwise as it does alone."""
+    name = "euler2d_q2"
+    solo = {}
+    for scheme in ("crkdg", "rkdg"):
+        params, o, mesh = _setup(lib, name, scheme=scheme)
+        C0 = random_state(o, seed=95, rel_amp=0.1)
+        slots = mesh.new_slots()
+        mesh.set_legendre(slots[0], C0)
+        ctl = mesh.new_ctl()
+        mesh.start(slots, ctl)
+        infos = [mesh.step(slots, ctl)[0] for _ in range(2)]
+        solo[scheme] = (infos[-1], mesh.get_legendre(slots[infos[-1]["cur"]]))
+    both = lib.Mesh([gpu_problem(dict(CASES[name], precision="fp64", scheme=s)) for s in ("crkdg", "rkdg")])
+    assert both.group_count() == 2
+    assert sorted(both.get_tuning(g)["scheme"] for g in range(2)) == [lib.SCHEME_CRKDG, lib.SCHEME_RKDG]
+    slots = both.new_slots()
+    for i in range(2):
+        both.set_legendre(slots[0], C0, inst=i)
+    ctl = both.new_ctl()
+    both.start(slots, ctl)
+    for _ in range(2):
+        infos = both.step(slots, ctl)
+    for i, scheme in enumerate(("crkdg", "rkdg")):
+        assert infos[i]["dt"] == solo[scheme][0]["dt"]
+        assert np.array_equal(both.get_legendre(slots[infos[i]["cur"]], inst=i), solo[scheme][1])

@@ -88,3 +88,6 @@ def test_init_rejects_bad_problems_without_gpu():
     assert b"dim" in crkdg.LIB.crkdg_last_error()
     p = crkdg.Problem(dim=1, n=(4,), k=5).to_c()
     assert crkdg.LIB.crkdg_init_mesh(ctypes.byref(p), 1, ctypes.byref(h), ctypes.byref(lay)) == crkdg.E_ARG
+    p = crkdg.Problem(dim=1, n=(4,), scheme=7).to_c()
+    assert crkdg.LIB.crkdg_init_mesh(ctypes.byref(p), 1, ctypes.byref(h), ctypes.byref(lay)) == crkdg.E_ARG
+    assert b"scheme" in crkdg.LIB.crkdg_last_error()

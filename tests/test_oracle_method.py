@@ -302,3 +302,50 @@ def test_burgers_matches_characteristics_before_the_shock():
         errs.append(o.l1_norm(U, exact)[0])
         assert o.bound_violations(U) == 0
     assert math.log2(errs[0] / errs[1]) > 2.5, errs
+
+
+def _attempt_matrix(o, dt, op):
+    n = o.ncell * o.M
+    Sm = np.zeros((n, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        Sm[:, j] = o.attempt(e.reshape(o.ncell, 1, o.M), dt, op)[0].reshape(-1)
+    return Sm
+
+
+@pytest.mark.parametrize("s,k", [(2, 1), (3, 2), (4, 3)])
+def test_standard_rkdg_step_is_truncated_exponential(s, k):
+    """The oracle's standard RKDG path (F in every stage, Sec. 2.1): an
+    s-stage Runge-Kutta method of order s <= 4 has the stability function
+    sum_{m<=s} z^m/m!, so without limiter the linear step is that polynomial
+    of dt F.  F is taken from the oracle; the polynomial is the closed form
+    and does not depend on the Butcher coefficients."""
+    o = CRKDG(Problem(dim=1, n=(5,), system=ADVECTION, k=k, stages=s, vel=(1.0, 0, 0), limiter=False))
+    n = o.ncell * o.M
+    dt = 0.13 * o.dx[0]
+    Fm = np.zeros((n, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        Fm[:, j] = o.F(e.reshape(o.ncell, 1, o.M)).reshape(-1)
+    ref = np.zeros((n, n))
+    term = np.eye(n)
+    for m in range(s + 1):
+        ref += term / math.factorial(m)
+        term = term @ (dt * Fm)
+    got = _attempt_matrix(o, dt, o.F)
+    assert np.max(np.abs(got - ref)) < 1e-12
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_standard_rkdg_stability_limit_against_paper(k):
+    """The standard RKDG path of the oracle (stage operator F) on a periodic
+    24-cell mesh is stable just below the paper's RKDG CFL limit (0.333 /
+    0.209 / 0.145, Sec. 3.2) and grows just above it; the matrix is built from
+    whole oracle attempts on unit vectors."""
+    o = CRKDG(Problem(dim=1, n=(24,), system=ADVECTION, k=k, stages=k + 1, vel=(1.0, 0, 0), limiter=False))
+    lim = GOLDEN["cfl_rkdg"]["values"][k - 1]
+    below = np.max(np.abs(np.linalg.eigvals(_attempt_matrix(o, (lim - 0.002) * o.dx[0], o.F))))
+    above = np.max(np.abs(np.linalg.eigvals(_attempt_matrix(o, (lim + 0.002) * o.dx[0], o.F))))
+    assert below <= 1.0 + 1e-10 and above > 1.0 + 1e-6
