@@ -13,12 +13,16 @@ averages / checks / limiter theta / average update); the plain FP64 form is
 timed on the same workload and reported beside it with the relative L1
 difference of the two after the same number of steps.
 
-Two more workloads are measured in the same run and reported under
+More workloads are measured in the same run and reported under
 "workloads" (a failure there is reported, never fatal to the headline):
-  euler3d  3D Euler, 128^3 periodic, Q^2 (27 modes x 5 variables), RK4
-           cRKDG, smooth translating density wave (rho = 1 + 0.99 sin);
-  batched  64 independent 2D Euler instances in one mesh, N_i ~ U{64..512},
-           P^1-P^3, 3 or 4 stages, 16-site Voronoi states, per-instance dt.
+  euler3d       3D Euler, 128^3 periodic, Q^2 (27 modes x 5 variables), RK4
+                cRKDG, smooth translating density wave (rho = 1 + 0.99 sin);
+  batched       64 independent 2D Euler instances in one mesh,
+                N_i ~ U{64..512}, P^1-P^3, 3 or 4 stages, 16-site Voronoi
+                states, per-instance dt;
+  euler2d_rkdg  the headline workload under the standard RKDG scheme (F in
+                every stage, same Butcher table and limiter), with the
+                cRKDG-over-RKDG step-time ratio.
 
 Metric: DOF-stage updates/s = sum over instances of Nc M V x executed stages
 / wall time, with the state resident in HBM before the timed region starts.
@@ -54,9 +58,10 @@ def parse():
     ap.add_argument("--n", type=int, default=1024, help="cells per direction of the headline workload")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
-    ap.add_argument("--workloads", default="euler3d,batched",
-                    help="extra workloads to measure (comma list of euler3d, batched; empty for none)")
-    ap.add_argument("--only", choices=["euler3d", "batched"], default=None,
+    ap.add_argument("--workloads", default="euler3d,batched,euler2d_rkdg",
+                    help="extra workloads to measure (comma list of euler3d, batched, euler2d_rkdg; "
+                         "empty for none)")
+    ap.add_argument("--only", choices=["euler3d", "batched", "euler2d_rkdg"], default=None,
                     help="run only this extra workload and print its results (for profiling)")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -91,13 +96,16 @@ def wave3d_state(mesh, state, case, n, torch):
 
 
 def setup(name, precision, crkdg, inputs, torch, n2d):
-    if name == "euler2d":
+    scheme = "crkdg"
+    if name in ("euler2d", "euler2d_rkdg"):
         cases = [inputs.euler_2d_voronoi(seed=0, n=n2d)]
+        if name == "euler2d_rkdg":
+            scheme = "rkdg"     # same workload, standard RKDG (F in every stage)
     elif name == "euler3d":
         cases = [inputs.euler_3d_wave(seed=0, n=128)]
     else:
         cases = inputs.batched_2d(seed=0)
-    probs = [crkdg.problem_from_params(dict(c.params, precision=precision)) for c in cases]
+    probs = [crkdg.problem_from_params(dict(c.params, precision=precision, scheme=scheme)) for c in cases]
     mesh = crkdg.Mesh(probs)
     slots = mesh.new_slots()
     if name == "euler3d":
@@ -397,6 +405,12 @@ def main():
         except Exception as e:  # reported, never fatal to the headline line
             extra[name] = {"error": f"{type(e).__name__}: {e}", "trace": traceback.format_exc()[-600:]}
         torch.cuda.empty_cache()
+    rk = extra.get("euler2d_rkdg")
+    if rk and "error" not in rk:
+        # what compactness buys: cRKDG step time against standard RKDG's on
+        # the same workload, kernels and launch-shape tuning
+        rk["crkdg_speedup_over_rkdg"] = {p: rk[p]["ms_per_step"] / (results[p]["ms"] / args.steps)
+                                         for p in results}
     if extra:
         line["workloads"] = extra
     if not args.no_cpu:
