@@ -49,6 +49,10 @@ design notes of the repository):
       S_K; theta is clamped to [0, 1].
   A10 a failed check restarts the whole step from u^n with dt/2.
   A13 outflow boundary: exterior trace = interior trace.
+  A21 reflective wall (Euler): exterior trace = the interior trace with the
+      momentum component normal to the wall negated (mirror state).
+  A22 Dirichlet / inflow boundary: exterior trace = the prescribed state of
+      that side (conservative variables), the same at every face point.
 """
 from __future__ import annotations
 
@@ -59,7 +63,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 ADVECTION, BURGERS, EULER = "advection", "burgers", "euler"
-PERIODIC, OUTFLOW = "periodic", "outflow"
+PERIODIC, OUTFLOW, REFLECT, DIRICHLET = "periodic", "outflow", "reflect", "dirichlet"
 
 # Butcher tables of the three cRKDG schemes (Sec. 3.3): explicit midpoint
 # (second order), Heun's third-order method, the classical fourth-order method.
@@ -175,7 +179,9 @@ class Problem:
     stages: int = 3
     lo: tuple = (0.0, 0.0, 0.0)
     hi: tuple = (1.0, 1.0, 1.0)
-    bc: tuple = (PERIODIC, PERIODIC, PERIODIC)
+    bc: tuple = (PERIODIC, PERIODIC, PERIODIC)   # per direction (both sides)
+    bc_upper: tuple = None        # per direction, upper side; None: as `bc`
+    bc_state: dict = field(default_factory=dict)  # side 2 d + (upper) -> Dirichlet state [V]
     vel: tuple = (1.0, 1.0, 1.0)  # advection velocity
     gamma: float = 1.4
     bound_lo: float = -math.inf   # scalar invariant region B = [m, M]
@@ -188,6 +194,12 @@ class Problem:
     @property
     def nvars(self):
         return self.dim + 2 if self.system == EULER else 1
+
+    def side_bc(self, dd, side):
+        """Boundary kind of the lower (side < 0) or upper side of direction dd."""
+        if side > 0 and self.bc_upper is not None:
+            return self.bc_upper[dd]
+        return self.bc[dd]
 
 
 # --------------------------------------------------------------------------
@@ -213,6 +225,17 @@ class CRKDG:
         if prob.space not in ("P", "Q"):
             raise ValueError("space must be P or Q")
         self.space = "Q" if d == 1 else prob.space
+        for dd in range(d):
+            kinds = (prob.side_bc(dd, -1), prob.side_bc(dd, 1))
+            if (PERIODIC in kinds) and kinds != (PERIODIC, PERIODIC):
+                raise ValueError("a periodic direction is periodic on both sides")
+            for j, kind in enumerate(kinds):
+                if kind not in (PERIODIC, OUTFLOW, REFLECT, DIRICHLET):
+                    raise ValueError(f"unknown boundary kind {kind}")
+                if kind == REFLECT and prob.system != EULER:
+                    raise ValueError("reflective walls are defined for the Euler equations")
+                if kind == DIRICHLET and len(prob.bc_state.get(2 * dd + j, ())) != self.V:
+                    raise ValueError("a Dirichlet side needs a state of V values")
 
         # (k+1)-point Gauss rule, tensor volume rule (weights sum to 2^d)
         g, wg = gauss_legendre(self.k + 1)
@@ -406,13 +429,14 @@ class CRKDG:
 
     # ---------------- mesh connectivity ----------------
     def neighbour(self, cells, dd, side):
-        """Neighbour cell across face (dd, side), or -1 on an outflow boundary."""
+        """Neighbour cell across face (dd, side), or -1 on a non-periodic
+        boundary."""
         ijk = self.idx[cells].copy()
         ijk[:, dd] += side
         nd = self.n[dd]
         out = np.zeros(len(cells), dtype=np.int64)
         bnd = (ijk[:, dd] < 0) | (ijk[:, dd] >= nd)
-        if self.p.bc[dd] == PERIODIC:
+        if self.p.side_bc(dd, side) == PERIODIC:
             ijk[:, dd] %= nd
             bnd[:] = False
         ijk[bnd, dd] = 0
@@ -465,6 +489,12 @@ class CRKDG:
         nb = self.neighbour(cells, face["dim"], face["side"])
         opp = [f for f in self.faces if f["dim"] == face["dim"] and f["side"] == -face["side"]][0]
         up = um.copy()                                      # outflow: u^ext = u^int (A13)
+        kind = self.p.side_bc(face["dim"], face["side"])
+        if kind == REFLECT:                                 # mirror state (A21)
+            up[..., 1 + face["dim"]] *= -1.0
+        elif kind == DIRICHLET:                             # prescribed state (A22)
+            j = 2 * face["dim"] + (1 if face["side"] > 0 else 0)
+            up[...] = np.asarray(self.p.bc_state[j], dtype=np.float64)
         inner = nb >= 0
         if np.any(inner):
             up[inner] = np.einsum("cvm,bm->cbv", U[nb[inner]], opp["phi"])

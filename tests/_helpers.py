@@ -20,7 +20,9 @@ def oracle_problem(params: dict) -> oracle.Problem:
         bc=bc, vel=tuple(params.get("vel", (1.0, 1.0, 1.0))), gamma=params.get("gamma", 1.4),
         bound_lo=params.get("bound_lo", -math.inf), bound_hi=params.get("bound_hi", math.inf),
         eps=params.get("eps", 1e-8), cfl=params.get("cfl", 0.1),
-        max_halvings=params.get("max_halvings", 40), limiter=bool(params.get("limiter", True)))
+        max_halvings=params.get("max_halvings", 40), limiter=bool(params.get("limiter", True)),
+        bc_upper=tuple(params["bc_upper"]) if params.get("bc_upper") else None,
+        bc_state=dict(params.get("bc_state", {})))
 
 
 def gpu_problem(params: dict):
