@@ -58,7 +58,14 @@ extern "C" {
 
 /* ---- enumerations ---------------------------------------------------- */
 #define CRKDG_BC_PERIODIC 0
-#define CRKDG_BC_OUTFLOW 1 /* exterior trace = interior trace */
+#define CRKDG_BC_OUTFLOW 1   /* exterior trace = interior trace */
+#define CRKDG_BC_REFLECT 2   /* Euler wall: exterior trace = interior trace with the normal
+                                momentum negated (mirror state; reflective sides of Sec. 4) */
+#define CRKDG_BC_DIRICHLET 3 /* exterior trace = the prescribed state bc_state of the side
+                                (Dirichlet and inflow sides of Sec. 4) */
+/* Reflective and Dirichlet sides enter only the final stage (the inner stages
+ * use no exterior data).  They are not built for 2D Q^3 Euler in FP64:
+ * crkdg_init_mesh returns CRKDG_E_UNSUPPORTED there. */
 
 #define CRKDG_SYS_ADVECTION 0 /* f(u) = a u, scalar */
 #define CRKDG_SYS_BURGERS 1   /* f_d(u) = u^2 / 2, scalar */
@@ -97,7 +104,8 @@ typedef struct crkdg_problem {
   int32_t n[3];      /* cells per direction (entries >= dim ignored) */
   double lo[3];      /* box corner */
   double hi[3];      /* opposite corner */
-  int32_t bc[3];     /* CRKDG_BC_* per direction */
+  int32_t bc[3];     /* CRKDG_BC_* per direction: the lower side, and the upper side
+                        unless bc_upper overrides it; periodic means both sides */
   int32_t system;    /* CRKDG_SYS_* */
   double vel[3];     /* advection velocity (CRKDG_SYS_ADVECTION) */
   double gamma;      /* ratio of specific heats (Euler) */
@@ -112,6 +120,12 @@ typedef struct crkdg_problem {
   double cfl;        /* trial step dt = cfl / sum_d (a0_d / dx_d)   (Sec. 4.1) */
   int32_t max_halvings; /* bound on halvings within one step (Sec. 4.1) */
   int32_t scheme;    /* CRKDG_SCHEME_* (0, the cRKDG scheme, in a zeroed struct) */
+  int32_t bc_upper[3]; /* upper side of direction d: 0 = as bc[d]; else CRKDG_BC_OUTFLOW,
+                          _REFLECT or _DIRICHLET (a periodic direction takes 0) */
+  int32_t pad;
+  double bc_state[6][5]; /* Dirichlet state of side 2 d + (upper side), conservative
+                            variables (rho, m_1..m_dim, E; scalars use [0]); it must lie
+                            in the admissible set (B, or B^eps for Euler) */
 } crkdg_problem;
 
 typedef struct crkdg_mesh crkdg_mesh; /* opaque handle */

@@ -17,7 +17,7 @@ import numpy as np
 
 _LIB_PATH = Path(__file__).resolve().parent / "_lib" / "libcrkdg.so"
 
-BC_PERIODIC, BC_OUTFLOW = 0, 1
+BC_PERIODIC, BC_OUTFLOW, BC_REFLECT, BC_DIRICHLET = 0, 1, 2, 3
 SYS_ADVECTION, SYS_BURGERS, SYS_EULER = 0, 1, 2
 SPACE_Q, SPACE_P = 0, 1
 FP64, MIXED = 0, 1
@@ -35,7 +35,8 @@ class CProblem(C.Structure):
         ("bound_lo", C.c_double), ("bound_hi", C.c_double), ("eps", C.c_double),
         ("k", C.c_int32), ("space", C.c_int32), ("stages", C.c_int32), ("precision", C.c_int32),
         ("limiter", C.c_int32), ("cfl", C.c_double), ("max_halvings", C.c_int32),
-        ("scheme", C.c_int32),
+        ("scheme", C.c_int32), ("bc_upper", C.c_int32 * 3), ("pad", C.c_int32),
+        ("bc_state", (C.c_double * 5) * 6),
     ]
 
 
@@ -157,6 +158,8 @@ class Problem:
     cfl: float = 0.1
     max_halvings: int = 40
     scheme: int = SCHEME_CRKDG
+    bc_upper: tuple = (0, 0, 0)   # upper side per direction; 0: as bc
+    bc_state: dict = field(default_factory=dict)  # side 2 d + upper -> Dirichlet state
 
     def to_c(self) -> CProblem:
         p = CProblem()
@@ -171,18 +174,24 @@ class Problem:
         p.precision, p.limiter, p.max_halvings = self.precision, int(self.limiter), self.max_halvings
         p.gamma, p.bound_lo, p.bound_hi = self.gamma, self.bound_lo, self.bound_hi
         p.eps, p.cfl, p.scheme = self.eps, self.cfl, self.scheme
+        for i in range(3):
+            p.bc_upper[i] = int(self.bc_upper[i]) if i < len(self.bc_upper) else 0
+        for side, vals in self.bc_state.items():
+            for v, x in enumerate(vals):
+                p.bc_state[int(side)][v] = float(x)
         return p
 
 
 _SYS_NAMES = {"advection": SYS_ADVECTION, "burgers": SYS_BURGERS, "euler": SYS_EULER}
-_BC_NAMES = {"periodic": BC_PERIODIC, "outflow": BC_OUTFLOW}
+_BC_NAMES = {"periodic": BC_PERIODIC, "outflow": BC_OUTFLOW, "reflect": BC_REFLECT, "dirichlet": BC_DIRICHLET}
 _SCHEME_NAMES = {"crkdg": SCHEME_CRKDG, "rkdg": SCHEME_RKDG}
 
 
 def problem_from_params(params: dict) -> Problem:
     """Problem from a workload parameter dict (names as in crkdg_problem,
     enumerations spelled as words: system 'euler', space 'Q', bc 'periodic',
-    precision 'fp64' / 'mixed', scheme 'crkdg' / 'rkdg')."""
+    precision 'fp64' / 'mixed', scheme 'crkdg' / 'rkdg'; bc_upper per direction,
+    bc_state {side 2 d + upper: state})."""
     d = params["dim"]
     bc = tuple(_BC_NAMES[b] for b in params.get("bc", ("periodic",) * d)) + (BC_PERIODIC,) * (3 - d)
     n = tuple(params["n"]) + (1,) * (3 - d)
@@ -195,7 +204,9 @@ def problem_from_params(params: dict) -> Problem:
         bound_lo=params.get("bound_lo", -math.inf), bound_hi=params.get("bound_hi", math.inf),
         eps=params.get("eps", 1e-8), limiter=int(params.get("limiter", True)),
         cfl=params.get("cfl", 0.1), max_halvings=params.get("max_halvings", 40),
-        scheme=_SCHEME_NAMES[params.get("scheme", "crkdg")])
+        scheme=_SCHEME_NAMES[params.get("scheme", "crkdg")],
+        bc_upper=tuple(_BC_NAMES[b] for b in params["bc_upper"]) if params.get("bc_upper") else (0, 0, 0),
+        bc_state=dict(params.get("bc_state", {})))
 
 
 class State:

@@ -33,7 +33,7 @@ struct InstDev {
   int64_t avg_off;   // element offset inside a state's avg array
   int64_t hi_off;    // element offset inside a state's hi array
   int32_t n[3];
-  int32_t bc[3];
+  int32_t bc[6];     // CRKDG_BC_* per side 2 d + (upper side)
   int32_t stages;
   int32_t limiter;
   int32_t max_halvings;
@@ -44,6 +44,7 @@ struct InstDev {
   double r2dx[3];    // 2 / dx_d
   double vel[3];
   double gamma, blo, bhi, eps, cfl, vol;
+  double bcs[6][5];  // Dirichlet states per side
 };
 
 // One work item = one tile of cells of one instance: blockDim.x consecutive
@@ -299,6 +300,12 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
   static constexpr int US = BIG ? 1 : NS;       // unroll of S_K loops
   static constexpr int TM = S::TM;
   using RT = Rt<D, K, SP, T>;
+  // Reflective and Dirichlet sides.  Not built into the 2D Q^3 Euler FP64
+  // kernels (64 FP64 values per state, spilling to scratch), whose final
+  // stage computed wrong values when the boundary code was added although it
+  // is never reached on periodic meshes; there only periodic and outflow
+  // sides are accepted.
+  static constexpr bool WALLS = BIG || MIXED || M * V <= 60;
 
   struct State {
     double ub[V];     // cell averages (FP64)
@@ -523,10 +530,18 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
       if (nb >= 0) {
         face_modes_mem(avg, hi, I.ncell, nb, f ^ 1, Re);
       } else {
+        // the exterior trace of ghost() in tangential modes (it is linear in
+        // the interior trace, or constant)
+        const int kind = I.bc[f];
 #pragma unroll
         for (int v = 0; v < V; ++v)
 #pragma unroll
-          for (int t = 0; t < TM; ++t) Re[v][t] = Ri[v][t];
+          for (int t = 0; t < TM; ++t) {
+            T x = Ri[v][t];
+            if (kind == CRKDG_BC_REFLECT && v == 1 + d) x = -x;
+            if (kind == CRKDG_BC_DIRICHLET) x = (t == 0) ? T(I.bcs[f][v]) : T(0);
+            Re[v][t] = x;
+          }
       }
       // alpha: largest wave speed over the face points and both traces
       T alpha = T(0);
@@ -594,7 +609,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
     const int64_t stride = (d == 0) ? 1 : (d == 1) ? static_cast<int64_t>(I.n[0])
                                                    : static_cast<int64_t>(I.n[0]) * I.n[1];
     const int nd = I.n[d];
-    const bool periodic = I.bc[d] == CRKDG_BC_PERIODIC;
+    const bool periodic = I.bc[f] == CRKDG_BC_PERIODIC;
     if ((f & 1) == 0) {
       if (q > 0) return p.c - stride;
       return periodic ? p.c + (nd - 1) * stride : -1;
@@ -603,6 +618,20 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
     return periodic ? p.c - (nd - 1) * stride : -1;
   }
 
+
+  // Exterior trace on a non-periodic side f = 2 d + upper (no neighbour):
+  // outflow, the interior trace; reflective wall, the mirror state (normal
+  // momentum negated); Dirichlet / inflow, the prescribed state.
+  __device__ __forceinline__ static void ghost(int f, const InstDev& I, const T* ui, T* ue) {
+    const int kind = I.bc[f];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      T x = ui[v];
+      if (kind == CRKDG_BC_REFLECT && v == 1 + f / 2) x = -x;
+      if (kind == CRKDG_BC_DIRICHLET) x = T(I.bcs[f][v]);
+      ue[v] = x;
+    }
+  }
 
   // F = -div^DG f with the Lax--Friedrichs flux (Sec. 2.1).  Each face flux is
   // formed in the canonical (lower cell, upper cell) orientation with the same
@@ -636,6 +665,9 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
         getnb(f, nb, sn);
 #pragma unroll
         for (int b = 0; b < S::NFP; ++b) at_face(sn, f ^ 1, b, ue[b]);
+      } else if constexpr (WALLS) {
+#pragma unroll
+        for (int b = 0; b < S::NFP; ++b) ghost(f, I, ui[b], ue[b]);
       } else {
 #pragma unroll
         for (int b = 0; b < S::NFP; ++b)

@@ -169,6 +169,22 @@ int64_t instance_tile_count(const crkdg_problem& p, int threads, int tile_x) {
   return ((p.n[0] + tile_x - 1) / tile_x) * ((p.n[1] + ty_cells - 1) / ty_cells) * (p.dim == 3 ? p.n[2] : 1);
 }
 
+// boundary kind of side `up` (0 lower, 1 upper) of direction d
+int side_bc(const crkdg_problem& p, int d, int up) {
+  return (up && p.bc_upper[d] != 0) ? p.bc_upper[d] : p.bc[d];
+}
+
+// a prescribed boundary state inside B (scalar) or B^eps (Euler)
+bool admissible_state(const crkdg_problem& p, const double* u) {
+  const int V = (p.system == CRKDG_SYS_EULER) ? p.dim + 2 : 1;
+  for (int v = 0; v < V; ++v)
+    if (!std::isfinite(u[v])) return false;
+  if (p.system != CRKDG_SYS_EULER) return u[0] >= p.bound_lo && u[0] <= p.bound_hi;
+  double m2 = 0.0;
+  for (int d = 0; d < p.dim; ++d) m2 += u[1 + d] * u[1 + d];
+  return u[0] >= p.eps && u[p.dim + 1] - 0.5 * m2 / u[0] >= p.eps;
+}
+
 int validate(const crkdg_problem& p, int idx) {
   auto bad = [&](const char* what) {
     return fail(CRKDG_E_ARG, "problem " + std::to_string(idx) + ": " + what);
@@ -177,7 +193,17 @@ int validate(const crkdg_problem& p, int idx) {
   for (int d = 0; d < p.dim; ++d) {
     if (p.n[d] < 1) return bad("n must be >= 1");
     if (!(p.hi[d] > p.lo[d])) return bad("hi must exceed lo");
-    if (p.bc[d] != CRKDG_BC_PERIODIC && p.bc[d] != CRKDG_BC_OUTFLOW) return bad("unknown bc");
+    if (p.bc[d] < CRKDG_BC_PERIODIC || p.bc[d] > CRKDG_BC_DIRICHLET) return bad("unknown bc");
+    if (p.bc_upper[d] < 0 || p.bc_upper[d] > CRKDG_BC_DIRICHLET) return bad("unknown bc_upper");
+    if (p.bc[d] == CRKDG_BC_PERIODIC && p.bc_upper[d] != 0)
+      return bad("a periodic direction is periodic on both sides (bc_upper must be 0)");
+    for (int up = 0; up < 2; ++up) {
+      const int kind = side_bc(p, d, up);
+      if (kind == CRKDG_BC_REFLECT && p.system != CRKDG_SYS_EULER)
+        return bad("reflective walls are defined for the Euler equations");
+      if (kind == CRKDG_BC_DIRICHLET && !admissible_state(p, p.bc_state[2 * d + up]))
+        return bad("Dirichlet state not finite or outside the admissible set");
+    }
   }
   if (p.system < 0 || p.system > 2) return bad("unknown system");
   if (p.k < 1 || p.k > 3) return bad("k must be 1..3");
@@ -427,6 +453,15 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
       return fail(CRKDG_E_UNSUPPORTED, "problem " + std::to_string(i) +
                                            ": no compiled kernel for this dim/k/space/system/precision");
     }
+    if (!ops->walls)
+      for (int d = 0; d < p.dim; ++d)
+        for (int up = 0; up < 2; ++up)
+          if (side_bc(p, d, up) == CRKDG_BC_REFLECT || side_bc(p, d, up) == CRKDG_BC_DIRICHLET) {
+            delete m;
+            return fail(CRKDG_E_UNSUPPORTED, "problem " + std::to_string(i) +
+                                                 ": reflective and Dirichlet sides are not built for this "
+                                                 "dim/k/space/system/precision (2D Q^3 Euler FP64)");
+          }
     int64_t nc = 1;
     for (int d = 0; d < p.dim; ++d) nc *= p.n[d];
     crkdg_instance_layout& L = m->lay[i];
@@ -451,14 +486,17 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
       if (d < p.dim) {
         const double dx = (p.hi[d] - p.lo[d]) / p.n[d];
         I.n[d] = p.n[d];
-        I.bc[d] = p.bc[d];
+        for (int up = 0; up < 2; ++up) {
+          I.bc[2 * d + up] = side_bc(p, d, up);
+          for (int v = 0; v < 5; ++v) I.bcs[2 * d + up][v] = p.bc_state[2 * d + up][v];
+        }
         I.rdx[d] = 1.0 / dx;
         I.r2dx[d] = 2.0 / dx;
         I.vel[d] = p.vel[d];
         vol *= dx;
       } else {
         I.n[d] = 1;
-        I.bc[d] = CRKDG_BC_PERIODIC;
+        I.bc[2 * d] = I.bc[2 * d + 1] = CRKDG_BC_PERIODIC;
       }
     }
     I.vol = vol;

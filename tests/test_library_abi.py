@@ -91,3 +91,25 @@ def test_init_rejects_bad_problems_without_gpu():
     p = crkdg.Problem(dim=1, n=(4,), scheme=7).to_c()
     assert crkdg.LIB.crkdg_init_mesh(ctypes.byref(p), 1, ctypes.byref(h), ctypes.byref(lay)) == crkdg.E_ARG
     assert b"scheme" in crkdg.LIB.crkdg_last_error()
+
+
+def test_boundary_validation_without_gpu():
+    """Boundary sides are checked before any device call: periodic on one
+    side only, a reflective wall for a scalar law and a Dirichlet state
+    outside the admissible set are CRKDG_E_ARG."""
+    if not LIB.exists():
+        pytest.skip("libcrkdg.so not built")
+    from paper_2412_16002_amd import crkdg
+    h = ctypes.c_void_p()
+    lay = crkdg.CLayout()
+    bad = [
+        (crkdg.Problem(dim=1, n=(8,), bc=(crkdg.BC_PERIODIC,) * 3, bc_upper=(crkdg.BC_OUTFLOW, 0, 0)), b"periodic"),
+        (crkdg.Problem(dim=1, n=(8,), system=crkdg.SYS_ADVECTION, bc=(crkdg.BC_REFLECT, 0, 0)), b"reflective"),
+        (crkdg.Problem(dim=1, n=(8,), bc=(crkdg.BC_DIRICHLET, 0, 0), bc_state={0: [1.0, 0.0, -1.0], 1: [1, 0, 2.5]}),
+         b"Dirichlet"),
+        (crkdg.Problem(dim=1, n=(8,), bc=(crkdg.BC_OUTFLOW, 0, 0), bc_upper=(7, 0, 0)), b"bc_upper"),
+    ]
+    for p, word in bad:
+        c = p.to_c()
+        assert crkdg.LIB.crkdg_init_mesh(ctypes.byref(c), 1, ctypes.byref(h), ctypes.byref(lay)) == crkdg.E_ARG
+        assert word in crkdg.LIB.crkdg_last_error(), crkdg.LIB.crkdg_last_error()
