@@ -168,6 +168,25 @@ def euler_3d_blast(seed=0, n=128, precision="mixed"):
     return Case("euler_3d_blast", params, cell_states=states, meta=dict(centre=c, radius=r))
 
 
+def sedov_2d(n=160, k=2, space="Q", precision="fp64", length=1.1, eps=1e-13):
+    """The Sedov blast of the 2D examples (Sec. 4.3): [0, 1.1]^2, rho = 1,
+    w = 0, E = 1e-12 except E = 0.244816 / dx^2 in the corner cell; reflective
+    walls on the lower sides, outflow on the upper ones (the blast's energy
+    makes the shock reach radius 1 at t = 1).  eps below the background
+    rho e (reading A6)."""
+    dx = length / n
+    E = np.full(n * n, 1e-12)
+    E[0] = 0.244816 / dx ** 2
+    states = np.zeros((n * n, 4))
+    states[:, 0] = 1.0
+    states[:, 3] = E
+    stages = 3 if k <= 2 else 4
+    params = dict(dim=2, n=(n, n), system="euler", k=k, space=space, stages=stages,
+                  cfl={1: 0.3, 2: 0.153, 3: 0.093}[k], eps=eps, hi=(length, length, 1.0),
+                  bc=("reflect", "reflect"), bc_upper=("outflow", "outflow"), precision=precision)
+    return Case("sedov_2d", params, cell_states=states, t_end=1.0, meta=dict(dx=dx, shock_radius=1.0))
+
+
 def euler_wave(dim, n, k, space="Q", stages=None, seed=0, precision="fp64", amp=0.99):
     """Exact smooth Euler solution in d dimensions: rho = 1 + amp sin(2 pi
     (sum x - d t) + phi), w = (1, .., 1), p = 1 (a translating density wave)."""
