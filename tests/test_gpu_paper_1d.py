@@ -1,0 +1,87 @@
+"""The 1D Euler Riemann examples of Sec. 4.2 with Dirichlet ends on the GPU:
+the Lax shock tube ([-5, 5], t = 1.3) and the double rarefaction ([-1, 1],
+t = 0.6), 200 cells, P^2 and P^3, FP64 and mixed.  Lockstep with the FP64
+oracle over the first steps, then the full run against the exact Riemann
+solution (relative L1 of the density averages), the boundary-flux identity
+of the Dirichlet ends, and zero bound violations."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from _helpers import gpu_problem, oracle_problem, rel_err_per_var
+from test_oracle_boundaries import PAPER_1D, _cons1, paper_1d_checks
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2412_16002_amd import crkdg
+    return crkdg
+
+
+def _params(name, k, precision):
+    e = PAPER_1D[name]
+    return dict(dim=1, n=(200,), system="euler", k=k, stages=3 if k <= 2 else 4, lo=(e["lo"], 0.0, 0.0),
+                hi=(e["hi"], 1.0, 1.0), bc=("dirichlet",), bc_state={0: _cons1(e["left"]), 1: _cons1(e["right"])},
+                cfl=0.153 if k == 2 else 0.093, eps=1e-13, precision=precision)
+
+
+@pytest.mark.parametrize("name", list(PAPER_1D))
+@pytest.mark.parametrize("k,precision", [(2, "fp64"), (3, "fp64"), (2, "mixed")])
+def test_paper_1d_example(lib, name, k, precision):
+    params = _params(name, k, precision)
+    o = oracle.CRKDG(oracle_problem(params))
+    x = o.cell_centres()[:, 0]
+    e = PAPER_1D[name]
+    avg = np.where((x < 0.0)[:, None], np.array(_cons1(e["left"]))[None, :], np.array(_cons1(e["right"]))[None, :])
+    U = o.limit(o.constant_state(avg))[0]
+    mesh = lib.Mesh(gpu_problem(params))
+    slots = mesh.new_slots()
+    mesh.set_legendre(slots[0], o.to_legendre(U))
+    ctl = mesh.new_ctl()
+    t_end = e["t_end"]
+    mesh.start(slots, ctl, t0=0.0, t_end=t_end)
+    T0 = mesh.totals(slots[0]).cpu().numpy().copy()
+    t = 0.0
+    for n in range(20):                      # lockstep with the oracle
+        U, io = o.step(U, t, t_end)
+        t = io["t"]
+        ig = mesh.step(slots, ctl)[0]
+        assert ig["status"] == 0 and ig["halvings"] == io["halvings"]
+        err = rel_err_per_var(mesh.get_legendre(slots[ig["cur"]]), o.to_legendre(U))
+        # near vacuum theta_2 amplifies round-off by ulp(rho_bar) / eps (the
+        # lockstep bound of the 1D Riemann configuration)
+        assert err < (1e-9 if precision == "fp64" else 1e-5)
+    _say(f"[{name} P{k} {precision}] lockstep 20 steps, last rel err {err:.1e}")
+    while True:
+        ig = mesh.step(slots, ctl)[0]
+        assert ig["status"] in (0, lib.S_DONE)
+        if mesh.ctl_read(ctl)[0]["status"] == lib.S_DONE:
+            break
+    c = mesh.ctl_read(ctl)[0]
+    assert math.isclose(c["t"], t_end, rel_tol=1e-14)
+    cur = slots[c["cur"]]
+    C = mesh.get_legendre(cur)
+    l1, rate = paper_1d_checks(name, C[:, :, 0], mesh.totals(cur).cpu().numpy() - T0, t_end)
+    viol = o.bound_violations(o.from_legendre(C))
+    _say(f"[{name} P{k} {precision}] t = {t_end}: {c['accepted']} steps, rel L1 of rho vs exact {l1:.4f}, "
+         f"boundary-flux identity error {rate:.1e}, violations {viol}, min rho {C[:, 0, 0].min():.3e}")
+    assert viol == 0
+    assert l1 < e["l1"]
+    if precision == "fp64":
+        assert rate < (1e-12 if name == "lax" else 1e-8) * np.max(np.abs(T0))
+    else:
+        # mixed form: the face flux values are FP32 (their sums FP64), so the
+        # Dirichlet fluxes carry the same FP32 rounding every step
+        assert rate < 1e-7 * np.max(np.abs(T0))
