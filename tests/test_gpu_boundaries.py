@@ -57,6 +57,9 @@ CASES = {
     "euler3d_q1_sides": dict(dim=3, n=(9, 7, 8), system="euler", k=1, stages=2, cfl=0.3,
                              bc=("dirichlet", "periodic", "reflect"), bc_upper=("outflow", "periodic", "reflect"),
                              bc_state={0: _cons(0.9, [0.3, 0.0, -0.1], 1.1)}),
+    "euler3d_p1_sides": dict(dim=3, n=(9, 7, 8), system="euler", k=1, space="P", stages=2, cfl=0.3,
+                             bc=("reflect", "dirichlet", "periodic"), bc_upper=("outflow", "reflect", "periodic"),
+                             bc_state={2: _cons(1.1, [0.2, 0.3, 0.0], 0.8)}),
     "euler3d_q2_sides": dict(dim=3, n=(9, 6, 5), system="euler", k=2, stages=4, cfl=0.15,
                              bc=("reflect", "periodic", "dirichlet"), bc_upper=("reflect", "periodic", "outflow"),
                              bc_state={4: _cons(1.2, [0.0, 0.2, 0.4], 0.9)}),

@@ -54,6 +54,9 @@ CASES = {
     "adv3d_q2": dict(dim=3, n=(7, 6, 5), system="advection", k=2, stages=3, vel=(1.0, 0.5, -0.3),
                      bound_lo=0.0, bound_hi=2.0, cfl=0.15),
     "euler3d_q2": dict(dim=3, n=(9, 10, 4), system="euler", k=2, stages=4, cfl=0.15),
+    "euler3d_p1": dict(dim=3, n=(9, 7, 8), system="euler", k=1, space="P", stages=2, cfl=0.3),
+    "adv3d_p2": dict(dim=3, n=(7, 6, 5), system="advection", k=2, space="P", stages=3, vel=(1.0, 0.5, -0.3),
+                     bound_lo=0.0, bound_hi=2.0, cfl=0.15),
 }
 FP64_TOL = 1e-12
 
@@ -123,7 +126,7 @@ def test_stage_parity(lib, name):
 
 
 @pytest.mark.parametrize("name", ["burgers1d_p2", "euler1d_p3_outflow", "euler2d_q2", "euler2d_p3",
-                                  "adv2d_q2", "euler3d_q1", "euler3d_q2"])
+                                  "adv2d_q2", "euler3d_q1", "euler3d_q2", "euler3d_p1", "adv3d_p2"])
 def test_step_parity(lib, name):
     """Three accepted steps through the device controller (adaptive dt from
     the fused wave-speed maximum) against the oracle's steps."""
@@ -196,7 +199,7 @@ def test_projection_parity(lib, name):
 
 
 @pytest.mark.parametrize("name", ["euler2d_q2", "euler2d_p3", "euler1d_p3_outflow", "burgers1d_p2",
-                                  "euler3d_q2"])
+                                  "euler3d_q2", "euler3d_p1", "adv3d_p2"])
 def test_mixed_stage_parity(lib, name):
     """Mixed precision (modes >= 1 and transforms in FP32, averages FP64): one
     stage from identical (FP32-representable) inputs within 1e-5 of the
