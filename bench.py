@@ -246,15 +246,24 @@ def measured_traffic():
     return d["traffic_bytes_per_launch"] if d.get("source_hash") == kernel_source_hash() else None
 
 
+# the sources the headline final-stage kernel and its launch are built from
+# (the 2D Q^2 Euler instantiation, the shared device code and tables, the
+# launchers, the host code that maps tiles to workgroups, the ABI header)
+HEADLINE_SOURCES = ("include/crkdg.h", "paper_2412_16002_amd/csrc/device.hpp",
+                    "paper_2412_16002_amd/csrc/tables.hpp", "paper_2412_16002_amd/csrc/variants.hpp",
+                    "paper_2412_16002_amd/csrc/variants_v2d_q12_euler.hip",
+                    "paper_2412_16002_amd/csrc/host.hip")
+
+
 def kernel_source_hash():
-    """Hash of the HIP sources, to tell whether committed counter data still
-    describe the kernels that run."""
+    """Hash of the sources of the headline kernel, to tell whether committed
+    counter data still describe the kernel that runs."""
     import hashlib
     from pathlib import Path
     h = hashlib.sha256()
-    for f in sorted((Path(ROOT) / "paper_2412_16002_amd" / "csrc").glob("*")):
-        h.update(f.name.encode())
-        h.update(f.read_bytes())
+    for name in HEADLINE_SOURCES:
+        h.update(name.encode())
+        h.update((Path(ROOT) / name).read_bytes())
     return h.hexdigest()[:16]
 
 
