@@ -330,8 +330,9 @@ def extra_workload(name, args, crkdg, inputs, torch, stream):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design "
-                                   "note (see the design document), not an implemented path",
+        print(json.dumps({"error": "the benchmark runs on one GPU only: sharding over several GPUs "
+                                   "(instances of a batch, or slabs of one mesh with one halo exchange "
+                                   "per step) is not implemented",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
     import torch
