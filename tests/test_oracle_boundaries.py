@@ -197,3 +197,49 @@ def test_paper_1d_riemann_examples_against_exact_solution(name):
     assert o.bound_violations(U) == 0
     assert l1 < PAPER_1D[name]["l1"]
     assert rate < (1e-12 if name == "lax" else 1e-8) * np.max(np.abs(T0))
+
+
+def heaviside_problem(k, n=200):
+    """Sec. 4.2 traveling Heaviside example: u0 = 1 on [0, 1], inflow u = 2
+    on the left (the upper bound of B = [1, 2]), outflow on the right."""
+    return Problem(dim=1, n=(n,), system=ADVECTION, k=k, stages=k + 1, vel=(1.0, 0, 0), bc=(DIRICHLET,),
+                   bc_upper=(OUTFLOW,), bc_state={0: [2.0]}, bound_lo=1.0, bound_hi=2.0,
+                   cfl=0.153 if k == 2 else 0.093)
+
+
+def test_average_check_round_off_margin():
+    """Reading A24: averages within 2^-40 max(1, |m|, |M|) of B pass the
+    check, larger excursions do not; infinite bounds stay disabled."""
+    o = CRKDG(heaviside_problem(2, n=4))
+    tau = o.average_slack()
+    assert tau == 2.0 ** -39
+    avg = np.array([[2.0], [2.0 + 2 * np.finfo(float).eps], [2.0 + 0.5 * tau], [2.0 + 2 * tau], [1.0 - 2 * tau]])
+    assert o.admissible_average(avg).tolist() == [True, True, True, False, False]
+    p = CRKDG(Problem(dim=1, n=(4,), system=ADVECTION, bound_lo=-np.inf, bound_hi=3.0, bc=(PERIODIC,)))
+    assert p.average_slack() == 3.0 * 2.0 ** -40
+    assert p.admissible_average(np.array([[-1e300], [3.0 + 2.0 ** -38]])).tolist() == [True, False]
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_heaviside_inflow_example(k):
+    """The inflow carries the upper bound itself, so the cell next to it sits
+    at 2 up to rounding: with exact comparisons the step was rejected at
+    every halving (2 + 1 ulp); with the margin of A24 the run reaches
+    t = 0.5 without halvings, inside [1, 2] at every S_K point, with the
+    inflow mass identity (t (2 - 1)) to round-off and the front at x = 0.5
+    (relative L1 of the averages to the exact step below 0.5%)."""
+    o = CRKDG(heaviside_problem(k))
+    U = o.project(lambda x: np.ones(x.shape[:-1] + (1,)))
+    m0 = o.totals(U)[0]
+    t, halvings = 0.0, 0
+    while t < 0.5:
+        U, info = o.step(U, t, 0.5)
+        t = info["t"]
+        halvings += info["halvings"]
+    x = o.cell_centres()[:, 0]
+    exact = np.where(x < 0.5, 2.0, 1.0)
+    avg = o.cell_average(U)[:, 0]
+    assert halvings == 0
+    assert o.bound_violations(U) == 0
+    assert abs(o.totals(U)[0] - m0 - 0.5) < 1e-13
+    assert np.sum(np.abs(avg - exact)) / np.sum(exact) < 0.005
