@@ -110,7 +110,9 @@ typedef struct crkdg_problem {
   double vel[3];     /* advection velocity (CRKDG_SYS_ADVECTION) */
   double gamma;      /* ratio of specific heats (Euler) */
   double bound_lo;   /* scalar invariant region B = [bound_lo, bound_hi] (Sec. 2.2.2); */
-  double bound_hi;   /*   +-INFINITY disables that side */
+  double bound_hi;   /*   +-INFINITY disables that side.  The stage check accepts cell
+                        averages within 2^-40 max(1, |bound_lo|, |bound_hi|) of B (finite
+                        bounds only): round-off where the data attain a bound */
   double eps;        /* Euler admissible set: rho >= eps and rho e >= eps (Sec. 2.2.3) */
   int32_t k;         /* polynomial degree, 1..3 */
   int32_t space;     /* CRKDG_SPACE_* */

@@ -44,6 +44,7 @@ struct InstDev {
   double r2dx[3];    // 2 / dx_d
   double vel[3];
   double gamma, blo, bhi, eps, cfl, vol;
+  double blo_chk, bhi_chk;  // scalar average check: B widened by a round-off margin
   double bcs[6][5];  // Dirichlet states per side
 };
 
@@ -724,7 +725,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
       const double rhoe = s.ub[D + 1] - 0.5 * ke / s.ub[0];
       return (s.ub[0] >= I.eps) && (rhoe >= I.eps);
     } else {
-      return (s.ub[0] >= I.blo) && (s.ub[0] <= I.bhi);
+      return (s.ub[0] >= I.blo_chk) && (s.ub[0] <= I.bhi_chk);
     }
   }
   __device__ __forceinline__ static bool average_finite(const State& s) {

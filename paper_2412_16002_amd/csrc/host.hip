@@ -507,6 +507,16 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
     I.gamma = p.gamma;
     I.blo = p.bound_lo;
     I.bhi = p.bound_hi;
+    {
+      // averages within 2^-40 max(1, |m|, |M|) of B pass the check: data
+      // that attain a bound leave averages a few ulp outside it by rounding
+      double mag = 1.0;
+      if (std::isfinite(p.bound_lo)) mag = std::max(mag, std::fabs(p.bound_lo));
+      if (std::isfinite(p.bound_hi)) mag = std::max(mag, std::fabs(p.bound_hi));
+      const double tau = std::ldexp(mag, -40);
+      I.blo_chk = p.bound_lo - tau;
+      I.bhi_chk = p.bound_hi + tau;
+    }
     I.eps = p.eps;
     I.cfl = p.cfl;
     m->max_stages = std::max(m->max_stages, p.stages);

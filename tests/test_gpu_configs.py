@@ -128,7 +128,7 @@ def test_euler_1d_riemann_run(lib):
     while True:
         info = mesh.step(slots, ctl)[0]
         steps += 1
-        assert info["status"] == 0
+        assert info["status"] == 0 and steps < 20000
         if steps % 200 == 0 or info["t"] >= 2e-4:
             Ug = o.from_legendre(mesh.get_legendre(slots[info["cur"]]))
             v = o.bound_violations(Ug)
