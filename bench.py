@@ -368,7 +368,7 @@ def main():
     mixed = results["mixed"]
     fin = mixed["final"]
     line = {
-        "metric": "DOF-stage updates/s",
+        "metric": "DOF-stage updates/s (mixed vs FP64, same L1 error); % HBM roofline",
         "value": mixed["value"],
         "unit": "DOF-stage updates/s",
         "n_gpus": 1,
