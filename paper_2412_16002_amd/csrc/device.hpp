@@ -355,6 +355,68 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
       u[v] = a;
     }
   }
+  // Face traces of 2D tensor spaces by sum factorisation: the restriction to
+  // the face, R_t = sum_a (+-1)^a c(a, t) (P_a(+-1) = (+-1)^a), then the 1D
+  // Legendre series at the Gauss points of the tangential direction, whose
+  // nodes come in pairs +-y (even and odd parts shared).  The same
+  // operations serve a cell's own trace and its neighbour's.
+  static constexpr bool SF = (D == 2) && S::TENSOR && !BIG;
+  static constexpr int mode_of(int a, int b) {
+    for (int m = 0; m < M; ++m)
+      if (S::modes.e[m][0] == a && S::modes.e[m][1] == b) return m;
+    return -1;
+  }
+  struct Leg1D {
+    double p[K + 1][K + 1];   // p[j][b] = P_b(y_j) at the Gauss nodes
+    constexpr Leg1D() : p{} {
+      for (int j = 0; j <= K; ++j)
+        for (int b = 0; b <= K; ++b) p[j][b] = leg(b, S::gx(j));
+    }
+  };
+  static constexpr Leg1D leg1d{};
+  __device__ __forceinline__ static T coef(const State& s, int v, int m) {
+    return m == 0 ? T(s.ub[v]) : s.ch[v][m - 1];
+  }
+  __device__ __forceinline__ static void face_traces(const State& s, int f, T (&u)[S::NFP][V]) {
+    if constexpr (SF) {
+      const int d = f / 2;
+      const bool up = (f & 1) != 0;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        T R[K + 1];
+#pragma unroll
+        for (int t = 0; t <= K; ++t) {
+          T acc = coef(s, v, d == 0 ? mode_of(0, t) : mode_of(t, 0));
+#pragma unroll
+          for (int a = 1; a <= K; ++a) {
+            const T c = coef(s, v, d == 0 ? mode_of(a, t) : mode_of(t, a));
+            acc = (up || (a % 2 == 0)) ? acc + c : acc - c;
+          }
+          R[t] = acc;
+        }
+#pragma unroll
+        for (int j = 0; j < (K + 2) / 2; ++j) {
+          const int jp = K - j;
+          T E = R[0];
+#pragma unroll
+          for (int b = 2; b <= K; b += 2) E = fma(T(leg1d.p[jp][b]), R[b], E);
+          if (jp == j) {
+            u[jp][v] = E;
+          } else {
+            T O = T(leg1d.p[jp][1]) * R[1];
+#pragma unroll
+            for (int b = 3; b <= K; b += 2) O = fma(T(leg1d.p[jp][b]), R[b], O);
+            u[jp][v] = E + O;
+            u[j][v] = E - O;
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int b = 0; b < S::NFP; ++b) at_face(s, f, b, u[b]);
+    }
+  }
+
   // S_K values in FP64 (limiter decisions are taken in FP64)
   __device__ __forceinline__ static double sk_var(const State& s, int p, int v) {
     double a = 0.0;
@@ -386,10 +448,56 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
     T sd[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) sd[d] = T(scale * I.r2dx[d]);
+    // 2D tensor spaces: the series along y at the rows of the Gauss grid
+    // first (t[v][j][a] = sum_b c(a, b) P_b(y_j), nodes in +-y pairs), then
+    // along x at each point
+    T trow[SF ? V : 1][SF ? K + 1 : 1][SF ? K + 1 : 1];
+    if constexpr (SF) {
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int a = 0; a <= K; ++a)
+#pragma unroll
+          for (int j = 0; j < (K + 2) / 2; ++j) {
+            const int jp = K - j;
+            T E = coef(s, v, mode_of(a, 0));
+#pragma unroll
+            for (int b = 2; b <= K; b += 2) E = fma(T(leg1d.p[jp][b]), coef(s, v, mode_of(a, b)), E);
+            if (jp == j) {
+              trow[v][jp][a] = E;
+            } else {
+              T O = T(leg1d.p[jp][1]) * coef(s, v, mode_of(a, 1));
+#pragma unroll
+              for (int b = 3; b <= K; b += 2) O = fma(T(leg1d.p[jp][b]), coef(s, v, mode_of(a, b)), O);
+              trow[v][jp][a] = E + O;
+              trow[v][j][a] = E - O;
+            }
+          }
+    }
 #pragma unroll UQ
     for (int q = 0; q < S::NQ; ++q) {
       T u[V];
-      at_vol(s, q, u);
+      if constexpr (SF) {
+        const int i = q % (K + 1), j = q / (K + 1);
+        const bool low = i < K - i;              // x_i < 0: odd part enters negated
+        const int ip = low ? K - i : i;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          T E = trow[v][j][0];
+#pragma unroll
+          for (int a = 2; a <= K; a += 2) E = fma(T(leg1d.p[ip][a]), trow[v][j][a], E);
+          if (2 * i == K) {
+            u[v] = E;
+          } else {
+            T O = T(leg1d.p[ip][1]) * trow[v][j][1];
+#pragma unroll
+            for (int a = 3; a <= K; a += 2) O = fma(T(leg1d.p[ip][a]), trow[v][j][a], O);
+            u[v] = low ? E - O : E + O;
+          }
+        }
+      } else {
+        at_vol(s, q, u);
+      }
       const auto a = P::aux(u, I);
 #pragma unroll
       for (int d = 0; d < D; ++d) {
@@ -591,12 +699,12 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
 #pragma unroll
     for (int f = 0; f < S::NF; ++f) {
       T fn[S::NFP][V];
+      T tr[S::NFP][V];
+      face_traces(s, f, tr);
 #pragma unroll
       for (int b = 0; b < S::NFP; ++b) {
-        T u[V];
-        at_face(s, f, b, u);
-        const auto a = P::aux(u, I);
-        P::flux(u, a, f / 2, I, fn[b]);
+        const auto a = P::aux(tr[b], I);
+        P::flux(tr[b], a, f / 2, I, fn[b]);
       }
       face_accum(f, fn, I, scale, r);
     }
@@ -659,13 +767,11 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
       const bool upper = (f & 1) != 0;   // this cell is the lower cell of the face
       const int64_t nb = neighbour(p, f, I);
       T ui[S::NFP][V], ue[S::NFP][V];
-#pragma unroll
-      for (int b = 0; b < S::NFP; ++b) at_face(s, f, b, ui[b]);
+      face_traces(s, f, ui);
       if (nb >= 0) {
         State sn;
         getnb(f, nb, sn);
-#pragma unroll
-        for (int b = 0; b < S::NFP; ++b) at_face(sn, f ^ 1, b, ue[b]);
+        face_traces(sn, f ^ 1, ue);
       } else if constexpr (WALLS) {
 #pragma unroll
         for (int b = 0; b < S::NFP; ++b) ghost(f, I, ui[b], ue[b]);
