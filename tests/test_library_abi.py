@@ -113,3 +113,19 @@ def test_boundary_validation_without_gpu():
         c = p.to_c()
         assert crkdg.LIB.crkdg_init_mesh(ctypes.byref(c), 1, ctypes.byref(h), ctypes.byref(lay)) == crkdg.E_ARG
         assert word in crkdg.LIB.crkdg_last_error(), crkdg.LIB.crkdg_last_error()
+
+
+def test_size_limits_without_gpu():
+    """A mesh of more than 2^31 - 1 cells in one instance is refused before
+    any device call (cell indices of one instance are 32-bit in the tile
+    maps)."""
+    if not LIB.exists():
+        pytest.skip("libcrkdg.so not built")
+    from paper_2412_16002_amd import crkdg
+    h = ctypes.c_void_p()
+    lay = crkdg.CLayout()
+    p = crkdg.Problem(dim=2, n=(65536, 65536, 1)).to_c()
+    assert crkdg.LIB.crkdg_init_mesh(ctypes.byref(p), 1, ctypes.byref(h), ctypes.byref(lay)) == crkdg.E_ARG
+    assert b"2^31" in crkdg.LIB.crkdg_last_error()
+    p = crkdg.Problem(dim=1, n=(0, 1, 1)).to_c()
+    assert crkdg.LIB.crkdg_init_mesh(ctypes.byref(p), 1, ctypes.byref(h), ctypes.byref(lay)) == crkdg.E_ARG
