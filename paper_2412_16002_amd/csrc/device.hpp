@@ -355,12 +355,13 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
       u[v] = a;
     }
   }
-  // Face traces of 2D tensor spaces by sum factorisation: the restriction to
-  // the face, R_t = sum_a (+-1)^a c(a, t) (P_a(+-1) = (+-1)^a), then the 1D
-  // Legendre series at the Gauss points of the tangential direction, whose
-  // nodes come in pairs +-y (even and odd parts shared).  The same
-  // operations serve a cell's own trace and its neighbour's.
-  static constexpr bool SF = (D == 2) && S::TENSOR && !BIG;
+  // Face traces of 2D spaces by sum factorisation: the restriction to the
+  // face, R_t = sum_a (+-1)^a c(a, t) (P_a(+-1) = (+-1)^a; total-degree
+  // spaces sum over the modes they have), then the 1D Legendre series at the
+  // Gauss points of the tangential direction, whose nodes come in pairs +-y
+  // (even and odd parts shared).  The same operations serve a cell's own
+  // trace and its neighbour's.
+  static constexpr bool SF = (D == 2) && !BIG;
   static constexpr int mode_of(int a, int b) {
     for (int m = 0; m < M; ++m)
       if (S::modes.e[m][0] == a && S::modes.e[m][1] == b) return m;
@@ -389,7 +390,9 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
           T acc = coef(s, v, d == 0 ? mode_of(0, t) : mode_of(t, 0));
 #pragma unroll
           for (int a = 1; a <= K; ++a) {
-            const T c = coef(s, v, d == 0 ? mode_of(a, t) : mode_of(t, a));
+            const int m = d == 0 ? mode_of(a, t) : mode_of(t, a);
+            if (m < 0) continue;
+            const T c = coef(s, v, m);
             acc = (up || (a % 2 == 0)) ? acc + c : acc - c;
           }
           R[t] = acc;
@@ -448,7 +451,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
     T sd[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) sd[d] = T(scale * I.r2dx[d]);
-    // 2D tensor spaces: the series along y at the rows of the Gauss grid
+    // 2D spaces: the series along y at the rows of the Gauss grid
     // first (t[v][j][a] = sum_b c(a, b) P_b(y_j), nodes in +-y pairs), then
     // along x at each point
     T trow[SF ? V : 1][SF ? K + 1 : 1][SF ? K + 1 : 1];
@@ -462,13 +465,17 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
             const int jp = K - j;
             T E = coef(s, v, mode_of(a, 0));
 #pragma unroll
-            for (int b = 2; b <= K; b += 2) E = fma(T(leg1d.p[jp][b]), coef(s, v, mode_of(a, b)), E);
-            if (jp == j) {
+            for (int b = 2; b <= K; b += 2)
+              if (mode_of(a, b) >= 0) E = fma(T(leg1d.p[jp][b]), coef(s, v, mode_of(a, b)), E);
+            if (jp == j || mode_of(a, 1) < 0) {
+              // middle node, or no odd y-mode in this column (total degree)
               trow[v][jp][a] = E;
+              trow[v][j][a] = E;
             } else {
               T O = T(leg1d.p[jp][1]) * coef(s, v, mode_of(a, 1));
 #pragma unroll
-              for (int b = 3; b <= K; b += 2) O = fma(T(leg1d.p[jp][b]), coef(s, v, mode_of(a, b)), O);
+              for (int b = 3; b <= K; b += 2)
+                if (mode_of(a, b) >= 0) O = fma(T(leg1d.p[jp][b]), coef(s, v, mode_of(a, b)), O);
               trow[v][jp][a] = E + O;
               trow[v][j][a] = E - O;
             }
