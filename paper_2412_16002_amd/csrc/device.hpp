@@ -534,15 +534,63 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
     const int d = f / 2;
     const double sc = scale * I.rdx[d];
     const T sct = T(sc);
-#pragma unroll
-    for (int b = 0; b < S::NFP; ++b)
+    if constexpr (SF) {
+      // sum factorised: h_t = sum_b wb_b P_t(y_b) g_b over the face points
+      // (pairs +-y share their sum and difference), then every mode m with
+      // normal degree a and tangential degree t takes pfac(m) side^(a+1) h_t
+      const bool up = (f & 1) != 0;
 #pragma unroll
       for (int v = 0; v < V; ++v) {
-        r.a0[v] = cmad(-S::tab.cface[f][b][0], sc * static_cast<double>(fn[b][v]), r.a0[v]);
-        const T g = sct * fn[b][v];
+        // mode 0 in FP64, in the same order in both cells of the face
 #pragma unroll
-        for (int m = 1; m < M; ++m) r.ah[v][m - 1] = cmad(-S::tab.cface[f][b][m], g, r.ah[v][m - 1]);
+        for (int b = 0; b < S::NFP; ++b)
+          r.a0[v] = cmad(-S::tab.cface[f][b][0], sc * static_cast<double>(fn[b][v]), r.a0[v]);
+        T sum[(K + 2) / 2], dif[(K + 2) / 2];
+#pragma unroll
+        for (int j = 0; j < (K + 2) / 2; ++j) {
+          const int jp = K - j;
+          const T gp = sct * fn[jp][v];
+          if (jp == j) {
+            sum[j] = gp;
+            dif[j] = T(0);
+          } else {
+            const T gm = sct * fn[j][v];
+            sum[j] = gp + gm;
+            dif[j] = gp - gm;
+          }
+        }
+        T h[K + 1];
+#pragma unroll
+        for (int t = 0; t <= K; ++t) {
+          T acc = T(0);
+#pragma unroll
+          for (int j = 0; j < (K + 2) / 2; ++j) {
+            const int jp = K - j;
+            const double w = S::tab.wb[jp] * leg1d.p[jp][t];
+            if (jp == j && (t % 2) == 1) continue;   // P_t(0) = 0 for odd t
+            acc = fma(T(w), (t % 2 == 0) ? sum[j] : dif[j], acc);
+          }
+          h[t] = acc;
+        }
+#pragma unroll
+        for (int m = 1; m < M; ++m) {
+          const int a = S::modes.e[m][d];
+          const int t = S::modes.e[m][1 - d];
+          const double kf = S::pfac(m) * ((up || ((a + 1) % 2 == 0)) ? 1.0 : -1.0);
+          r.ah[v][m - 1] = cmad(-kf, h[t], r.ah[v][m - 1]);
+        }
       }
+    } else {
+#pragma unroll
+      for (int b = 0; b < S::NFP; ++b)
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          r.a0[v] = cmad(-S::tab.cface[f][b][0], sc * static_cast<double>(fn[b][v]), r.a0[v]);
+          const T g = sct * fn[b][v];
+#pragma unroll
+          for (int m = 1; m < M; ++m) r.ah[v][m - 1] = cmad(-S::tab.cface[f][b][m], g, r.ah[v][m - 1]);
+        }
+    }
   }
 
   // --- faces of the large spaces (BIG), tensor spaces only -----------------

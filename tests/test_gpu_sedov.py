@@ -12,7 +12,8 @@ ones, all the blast energy in the corner cell, background pressure 4e-13.
   t^(1/2), so the radius at t = 1/16 is 1/4.  The run stops there because
   the time step collapses near the corner, where the density falls to eps and
   the sound speed grows without bound (about 25k steps reach t = 1/16 and
-  100k steps t = 0.16)."""
+  100k steps t = 0.16; the mixed form, with wave speeds from FP32 point
+  values, takes more steps there)."""
 import math
 import sys
 
@@ -80,10 +81,10 @@ def test_sedov_paper_resolution(lib, precision):
     tot0 = mesh.totals(slots[0]).cpu().numpy().copy()
     graph = mesh.graph(slots, ctl, attempts=500)
     done = False
-    for r in range(120):
+    for r in range(400):                    # up to 200k attempts (dt collapses near the corner)
         graph.launch()
         c = mesh.ctl_read(ctl)[0]
-        if r % 20 == 0:
+        if r % 40 == 0:
             _say(f"[sedov {precision}] t {c['t']:.4f} accepted {c['accepted']} rejected {c['rejected']}")
         assert c["status"] in (0, lib.S_DONE)
         if c["status"] == lib.S_DONE:
