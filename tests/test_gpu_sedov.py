@@ -11,9 +11,9 @@ ones, all the blast energy in the corner cell, background pressure 4e-13.
   t = 1; the cylindrical blast is self-similar with radius growing like
   t^(1/2), so the radius at t = 1/16 is 1/4.  The run stops there because
   the time step collapses near the corner, where the density falls to eps and
-  the sound speed grows without bound (about 25k steps reach t = 1/16 and
-  100k steps t = 0.16; the mixed form, with wave speeds from FP32 point
-  values, takes more steps there)."""
+  the sound speed grows without bound: the step count to t = 1/16 depends on
+  rounding there (15k-25k steps in FP64, 40k-65k in the mixed form, whose
+  wave speeds come from FP32 point values; 100k FP64 steps reach t = 0.16)."""
 import math
 import sys
 
