@@ -102,3 +102,52 @@ def test_near_vacuum_density_wave_converges(lib, k):
     assert math.log2(ef[-2] / ef[-1]) > k + 1 - 0.3
     for a, b in zip(ef, em):
         assert b < a + 2e-7 and (a < 1e-5 or abs(b - a) < 0.01 * a)
+
+
+def _advection_l2(o, U, T):
+    g, w = np.polynomial.legendre.leggauss(o.k + 3)
+    X = o.physical_points(g[:, None])
+    vals = o.evaluate(U, g[:, None])[:, 0, :]
+    ex = np.sin(2 * np.pi * (X[..., 0] - T)) + 2.0
+    return math.sqrt(np.sum(w * (vals - ex) ** 2) * o.dx[0] / 2)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_table1_advection_on_gpu(lib, k):
+    """The 1D advection accuracy example (Sec. 4.2, Table 1 settings: u0 =
+    sin(2 pi x) + 2, t = 0.1024, the table's meshes and fixed steps; periodic
+    here): the FP64 library's L2 errors equal the oracle's to 1e-9 relative
+    and fall at order k+1; the mixed form matches while far above FP32
+    rounding."""
+    import json
+    from pathlib import Path
+    golden = json.loads((Path(__file__).parent / "golden" / "paper_constants.json").read_text())["table1"]
+    T = golden["T"]
+    errs = {"oracle": [], "fp64": [], "mixed": []}
+    for N, dt in zip(golden[f"k{k}"]["dx"][:3], golden["dt"][:3]):
+        params = dict(dim=1, n=(N,), system="advection", k=k, stages=k + 1, vel=(1.0, 0.0, 0.0), bound_lo=1.0,
+                      bound_hi=3.0, cfl=0.1)
+        o = oracle.CRKDG(oracle_problem(dict(params, precision="fp64")))
+        U0 = o.limit(o.project(lambda x: np.sin(2 * np.pi * x) + 2.0))[0]
+        nsteps = int(round(T / dt))
+        U = U0
+        for _ in range(nsteps):
+            U, _ = o.step(U, dt_fixed=dt)
+        errs["oracle"].append(_advection_l2(o, U, T))
+        for precision in ("fp64", "mixed"):
+            mesh = lib.Mesh(gpu_problem(dict(params, precision=precision)))
+            slots = mesh.new_slots()
+            mesh.set_legendre(slots[0], o.to_legendre(U0))
+            ctl = mesh.new_ctl()
+            mesh.start(slots, ctl, t0=0.0, dt_fixed=dt)
+            for _ in range(nsteps):
+                info = mesh.step(slots, ctl)[0]
+                assert info["status"] == 0 and info["halvings"] == 0
+            errs[precision].append(_advection_l2(o, o.from_legendre(mesh.get_legendre(slots[info["cur"]])), T))
+    _say(f"[table 1, k = {k}] oracle {['%.4e' % e for e in errs['oracle']]}, fp64 {['%.4e' % e for e in errs['fp64']]}, "
+         f"mixed {['%.4e' % e for e in errs['mixed']]}, paper {golden[f'k{k}']['err'][:3]}")
+    for eo, ef, em in zip(errs["oracle"], errs["fp64"], errs["mixed"]):
+        assert abs(ef - eo) < 1e-9 * eo
+        assert em < ef + 1e-6 and (ef < 1e-4 or abs(em - ef) < 0.01 * ef)
+    rates = [math.log2(a / b) for a, b in zip(errs["fp64"], errs["fp64"][1:])]
+    assert min(rates) > k + 1 - 0.25
