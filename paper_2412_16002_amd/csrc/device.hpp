@@ -420,6 +420,85 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
     }
   }
 
+  // Point values of the S_K set of 2D spaces by sum factorisation: the set is
+  // (Lobatto in x) x (Gauss in y) and (Gauss in x) x (Lobatto in y); each
+  // family is evaluated row by row (the series in y at the row's node, then
+  // in x), with the symmetric nodes +-y and +-x paired.  fn(u) is called for
+  // every point (the centre twice when both rules contain 0, which the
+  // order-free min/max checks do not notice).  Every value is reached through
+  // at most 2K + 3 roundings of partial sums bounded by |ubar| + sum |c_m|.
+  struct LegL {
+    double p[S::NL][K + 1];   // p[l][b] = P_b(x_l) at the Gauss--Lobatto nodes
+    constexpr LegL() : p{} {
+      for (int l = 0; l < S::NL; ++l)
+        for (int b = 0; b <= K; ++b) p[l][b] = leg(b, S::lx(l));
+    }
+  };
+  static constexpr LegL legl{};
+  template <typename Fn>
+  __device__ __forceinline__ static void sk_points_sf(const State& s, Fn&& fn) {
+    static_for<2>([&](auto FAM) {
+      constexpr int fam = decltype(FAM)::value;
+      constexpr int NR = (fam == 0) ? K + 1 : S::NL;   // rows (y nodes)
+      constexpr int NX = (fam == 0) ? S::NL : K + 1;   // points of a row (x nodes)
+#pragma unroll
+      for (int r = 0; r < (NR + 1) / 2; ++r) {
+        const int rp = NR - 1 - r;                      // y_rp >= 0, y_r = -y_rp
+        T tp[V][K + 1], tm[V][K + 1];
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+#pragma unroll
+          for (int a = 0; a <= K; ++a) {
+            T E = coef(s, v, mode_of(a, 0)), O = T(0);
+            bool odd = false;
+#pragma unroll
+            for (int b = 1; b <= K; ++b) {
+              const int m = mode_of(a, b);
+              if (m < 0) continue;
+              const double pb = (fam == 0) ? leg1d.p[rp][b] : legl.p[rp][b];
+              if (b % 2 == 0) {
+                E = cmad(pb, coef(s, v, m), E);
+              } else if (pb != 0.0) {
+                O = odd ? cmad(pb, coef(s, v, m), O) : T(pb) * coef(s, v, m);
+                odd = true;
+              }
+            }
+            tp[v][a] = odd ? E + O : E;
+            tm[v][a] = odd ? E - O : E;
+          }
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          if (side == 1 && rp == r) continue;           // the row at y = 0 once
+          const auto& t = side == 0 ? tp : tm;
+#pragma unroll
+          for (int c = 0; c < (NX + 1) / 2; ++c) {
+            const int cp = NX - 1 - c;                  // x_cp >= 0
+            T up[V], um[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+              T E = t[v][0], O = T(0);
+              bool odd = false;
+#pragma unroll
+              for (int a = 1; a <= K; ++a) {
+                const double pa = (fam == 0) ? legl.p[cp][a] : leg1d.p[cp][a];
+                if (a % 2 == 0) {
+                  E = cmad(pa, t[v][a], E);
+                } else if (pa != 0.0) {
+                  O = odd ? cmad(pa, t[v][a], O) : T(pa) * t[v][a];
+                  odd = true;
+                }
+              }
+              up[v] = odd ? E + O : E;
+              um[v] = odd ? E - O : E;
+            }
+            fn(up);
+            if (cp != c) fn(um);
+          }
+        }
+      }
+    });
+  }
+
   // S_K values in FP64 (limiter decisions are taken in FP64)
   __device__ __forceinline__ static double sk_var(const State& s, int p, int v) {
     double a = 0.0;
@@ -934,8 +1013,10 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
   // wave speeds of the points into a0[].  FP64: the exact tests of the
   // limiter.  Mixed: FP32 evaluation with a rigorous bound on its rounding
   // error (each value is a sum of at most M terms bounded by
-  // B = |ubar| + sum |c_m|, since |phi_m| <= 1 on the cell), so "pass" in FP32
-  // implies "pass" in FP64; near the bounds the FP64 limiter decides.
+  // B = |ubar| + sum |c_m|, since |phi_m| <= 1 on the cell; the sum-factorised
+  // 2D evaluation takes at most 2K + 3 <= M + 1 roundings of partial sums
+  // bounded by B), so "pass" in FP32 implies "pass" in FP64; near the bounds
+  // the FP64 limiter decides.
   template <bool A0>
   __device__ __forceinline__ static bool sk_pass(const State& s, const InstDev& I, double* a0) {
     T ub[V], err[V], bnd[V];
@@ -969,19 +1050,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
         thr_rho *= T(1 + 0x1p-20);
       }
       const T eps = T(I.eps);
-#pragma unroll US
-      for (int p = 0; p < NS; ++p) {
-        T u[V];
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          T a = ub[v];
-#pragma unroll
-          for (int m = 1; m < M; ++m) {
-            if constexpr (BIG) a = fma(RT::tab.phi_s[p][m], s.ch[v][m - 1], a);
-            else a = cmad(S::tab.phi_s[p][m], s.ch[v][m - 1], a);
-          }
-          u[v] = a;
-        }
+      auto check = [&](const T* u) {
         T ke = T(0);
 #pragma unroll
         for (int j = 0; j < D; ++j) ke = fma(u[1 + j], u[1 + j], ke);
@@ -994,17 +1063,30 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
 #pragma unroll
           for (int d = 0; d < D; ++d) a0[d] = fmax(a0[d], static_cast<double>(P::speed(u, ax, d, I)));
         }
+      };
+      if constexpr (SF) {
+        sk_points_sf(s, check);
+      } else {
+#pragma unroll US
+        for (int p = 0; p < NS; ++p) {
+          T u[V];
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            T a = ub[v];
+#pragma unroll
+            for (int m = 1; m < M; ++m) {
+              if constexpr (BIG) a = fma(RT::tab.phi_s[p][m], s.ch[v][m - 1], a);
+              else a = cmad(S::tab.phi_s[p][m], s.ch[v][m - 1], a);
+            }
+            u[v] = a;
+          }
+          check(u);
+        }
       }
     } else {
       const double lo = I.blo, hi = I.bhi;
-#pragma unroll US
-      for (int p = 0; p < NS; ++p) {
-        T a = ub[0];
-#pragma unroll
-        for (int m = 1; m < M; ++m) {
-          if constexpr (BIG) a = fma(RT::tab.phi_s[p][m], s.ch[0][m - 1], a);
-          else a = cmad(S::tab.phi_s[p][m], s.ch[0][m - 1], a);
-        }
+      auto check = [&](const T* pa) {
+        const T a = pa[0];
         const double u = static_cast<double>(a);
         const double e = static_cast<double>(err[0]);
         ok = ok && (u - e >= lo) && (u + e <= hi);
@@ -1012,6 +1094,20 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
           const auto ax = P::aux(&a, I);
 #pragma unroll
           for (int d = 0; d < D; ++d) a0[d] = fmax(a0[d], static_cast<double>(P::speed(&a, ax, d, I)));
+        }
+      };
+      if constexpr (SF) {
+        sk_points_sf(s, check);
+      } else {
+#pragma unroll US
+        for (int p = 0; p < NS; ++p) {
+          T a = ub[0];
+#pragma unroll
+          for (int m = 1; m < M; ++m) {
+            if constexpr (BIG) a = fma(RT::tab.phi_s[p][m], s.ch[0][m - 1], a);
+            else a = cmad(S::tab.phi_s[p][m], s.ch[0][m - 1], a);
+          }
+          check(&a);
         }
       }
     }
