@@ -54,9 +54,30 @@ def build(verbose: bool = True) -> Path:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-8000:]}")
     os.replace(tmp, LIB)
+    _build_c_demo()
     if verbose:
         print(f"built {LIB} from {len(srcs)} sources in {time.time() - t0:.1f}s", flush=True)
     return LIB
+
+
+# a plain C caller of the library (tests/c/step_demo.c), run by the GPU tests
+C_DEMO_SRC = ROOT / "tests" / "c" / "step_demo.c"
+C_DEMO = OUT_DIR / "step_demo"
+
+
+def _build_c_demo():
+    if not C_DEMO_SRC.exists():
+        return
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        return
+    rocm = Path(os.environ.get("ROCM_PATH", "/opt/rocm"))
+    cmd = [cc, "-O2", "-std=c11", "-Wall", f"-I{ROOT / 'include'}", f"-I{rocm / 'include'}",
+           "-D__HIP_PLATFORM_AMD__", str(C_DEMO_SRC), f"-L{OUT_DIR}", "-lcrkdg", f"-L{rocm / 'lib'}",
+           "-lamdhip64", "-Wl,-rpath,$ORIGIN", f"-Wl,-rpath,{rocm / 'lib'}", "-o", str(C_DEMO)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"building the C caller failed:\n{r.stderr[-4000:]}")
 
 
 if __name__ == "__main__":
