@@ -14,14 +14,19 @@
  * F = -div^DG f with the Lax--Friedrichs flux (Sec. 2.1), the Butcher tables of
  * Sec. 3.3, the scaling limiters of Sec. 2.2.2 (scalar, Prop. 2.4) and
  * Sec. 2.2.3 (Euler, density then internal energy), and the adaptive halving
- * strategy of Sec. 4.1.
+ * strategy of Sec. 4.1.  Options of each problem: the standard RKDG scheme
+ * of Sec. 2.1 instead (F in every stage, scheme = CRKDG_SCHEME_RKDG), and
+ * periodic, outflow, reflective or Dirichlet / inflow sides.
  *
  * Conventions shared by every entry point
  * ----------------------------------------
  * - All pointers whose name starts with d_ or that live inside crkdg_state are
  *   DEVICE pointers owned by the caller; the library never frees or allocates
- *   them, and allocates nothing per call (only the mesh handle and its small
- *   device tables, created by crkdg_init_mesh and freed by crkdg_free_mesh).
+ *   them.  The library's own device memory is allocated by crkdg_init_mesh
+ *   (basis tables, tile maps, and the deferred-limiter queue: room for one
+ *   record per cell, about one state's size) and freed by crkdg_free_mesh;
+ *   crkdg_set_tuning may grow a tile map and crkdg_graph_create builds a
+ *   graph.  The stepping entry points allocate nothing.
  * - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
  *   asynchronously unless an entry point says it synchronises.
  * - Return value: 0 on success; negative = usage or runtime error
