@@ -1,0 +1,29 @@
+"""The benchmark's command-line contract on the CPU (no GPU work): more than
+one GPU is refused with a JSON message and exit status 2; the counter data
+committed under profiles/ are reported only for the sources they describe."""
+import json
+import subprocess
+import sys
+from pathlib import Path
+
+ROOT = Path(__file__).resolve().parents[1]
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, str(ROOT / "bench.py"), "--gpus", "2", "--steps", "1"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]
+
+
+
+def test_traffic_counters_are_used_only_for_the_sources_they_describe():
+    """bench.py reports the committed HBM byte counters only while their
+    source hash matches the headline kernel's current sources."""
+    sys.path.insert(0, str(ROOT))
+    import bench
+    f = ROOT / "profiles" / "traffic_final_stage_euler2d_q2_1024_mixed.json"
+    d = json.loads(f.read_text())
+    expected = d["traffic_bytes_per_launch"] if d["source_hash"] == bench.kernel_source_hash() else None
+    assert bench.measured_traffic() == expected
