@@ -38,6 +38,10 @@ Readings of the paper where it is silent or ambiguous (also listed in the
 design notes of the repository):
   A1  LF alpha is taken per face: max over that face's quadrature points and
       both traces of |w.nu| + c (symmetric between the two cells of a face).
+      Optional (Problem.alpha = "point"): alpha at each face quadrature point
+      from its two traces alone (local LF); Prop. 2.1's bound argument holds
+      pointwise, since each point's alpha still bounds the wave speed of both
+      of its traces.
   A2  multi-D trial step: dt = CFL / sum_d (a0_d / dx_d)  (1D: CFL dx / a0).
   A4  S_K = union over d of (Gauss^{k+1} in the other directions x
       Gauss--Lobatto^N in direction d), N = 2 for k = 1, N = 3 for k = 2, 3.
@@ -194,6 +198,7 @@ class Problem:
     cfl: float = 0.1
     max_halvings: int = 40
     limiter: bool = True
+    alpha: str = "face"           # LF alpha per face (A1) or per face point
 
     @property
     def nvars(self):
@@ -228,6 +233,8 @@ class CRKDG:
         self.vol = float(np.prod(self.dx))
         if prob.space not in ("P", "Q"):
             raise ValueError("space must be P or Q")
+        if prob.alpha not in ("face", "point"):
+            raise ValueError("alpha must be face or point")
         self.space = "Q" if d == 1 else prob.space
         for dd in range(d):
             kinds = (prob.side_bc(dd, -1), prob.side_bc(dd, 1))
@@ -481,10 +488,12 @@ class CRKDG:
     def lf_flux(self, um, up, dd, side):
         """Lax--Friedrichs flux f^.nu on a face with outward normal side*e_dd
         (Sec. 2.1); um/up [c, b, V] interior/exterior traces.  alpha per face
-        (reading A1)."""
-        a = np.maximum(self.wave_speed(um, dd).max(axis=1), self.wave_speed(up, dd).max(axis=1))
+        (reading A1) or, with alpha = "point", per face point."""
+        a = np.maximum(self.wave_speed(um, dd), self.wave_speed(up, dd))     # [c, b]
+        if self.p.alpha == "face":
+            a = np.broadcast_to(a.max(axis=1)[:, None], a.shape)
         return (0.5 * side * (self.flux(um, dd) + self.flux(up, dd))
-                - 0.5 * a[:, None, None] * (up - um))
+                - 0.5 * a[:, :, None] * (up - um))
 
     def face_traces(self, U, cells, face):
         """Interior and exterior traces on `face` of `cells` -> ([c,b,V], [c,b,V])."""

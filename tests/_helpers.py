@@ -22,7 +22,7 @@ def oracle_problem(params: dict) -> oracle.Problem:
         eps=params.get("eps", 1e-8), cfl=params.get("cfl", 0.1),
         max_halvings=params.get("max_halvings", 40), limiter=bool(params.get("limiter", True)),
         bc_upper=tuple(params["bc_upper"]) if params.get("bc_upper") else None,
-        bc_state=dict(params.get("bc_state", {})))
+        bc_state=dict(params.get("bc_state", {})), alpha=params.get("alpha", "face"))
 
 
 def gpu_problem(params: dict):
