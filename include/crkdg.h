@@ -83,6 +83,13 @@ extern "C" {
 #define CRKDG_SCHEME_RKDG 1  /* standard RKDG (Sec. 2.1): F in every stage, same Butcher table,
                                 limiter and check after every stage */
 
+#define CRKDG_ALPHA_FACE 0  /* Lax-Friedrichs alpha per face: largest wave speed over the face's
+                               quadrature points and both traces (the reading of Sec. 2.1 used
+                               throughout) */
+#define CRKDG_ALPHA_POINT 1 /* alpha at each face quadrature point from its two traces (local
+                               Lax-Friedrichs / Rusanov); not built for 3D Q^2 Euler, whose
+                               init call returns CRKDG_E_UNSUPPORTED */
+
 #define CRKDG_FP64 0  /* every mode and all arithmetic in FP64 */
 #define CRKDG_MIXED 1 /* modes >= 1 and transforms/fluxes in FP32; averages,
                          admissibility checks, limiter theta and the
@@ -129,7 +136,7 @@ typedef struct crkdg_problem {
   int32_t scheme;    /* CRKDG_SCHEME_* (0, the cRKDG scheme, in a zeroed struct) */
   int32_t bc_upper[3]; /* upper side of direction d: 0 = as bc[d]; else CRKDG_BC_OUTFLOW,
                           _REFLECT or _DIRICHLET (a periodic direction takes 0) */
-  int32_t pad;
+  int32_t alpha;     /* CRKDG_ALPHA_* (0, per face, in a zeroed struct) */
   double bc_state[6][5]; /* Dirichlet state of side 2 d + (upper side), conservative
                             variables (rho, m_1..m_dim, E; scalars use [0]); it must lie
                             in the admissible set (B, or B^eps for Euler) */

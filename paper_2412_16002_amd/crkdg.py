@@ -22,6 +22,7 @@ SYS_ADVECTION, SYS_BURGERS, SYS_EULER = 0, 1, 2
 SPACE_Q, SPACE_P = 0, 1
 FP64, MIXED = 0, 1
 SCHEME_CRKDG, SCHEME_RKDG = 0, 1
+ALPHA_FACE, ALPHA_POINT = 0, 1
 E_ARG, E_HIP, E_UNSUPPORTED, E_LAYOUT = -1, -2, -3, -4
 S_REJECTED, S_DT_UNDERFLOW, S_NONFINITE, S_DONE = 1, 2, 3, 4
 F_AVERAGE, F_NONFINITE = 1, 2
@@ -35,7 +36,7 @@ class CProblem(C.Structure):
         ("bound_lo", C.c_double), ("bound_hi", C.c_double), ("eps", C.c_double),
         ("k", C.c_int32), ("space", C.c_int32), ("stages", C.c_int32), ("precision", C.c_int32),
         ("limiter", C.c_int32), ("cfl", C.c_double), ("max_halvings", C.c_int32),
-        ("scheme", C.c_int32), ("bc_upper", C.c_int32 * 3), ("pad", C.c_int32),
+        ("scheme", C.c_int32), ("bc_upper", C.c_int32 * 3), ("alpha", C.c_int32),
         ("bc_state", (C.c_double * 5) * 6),
     ]
 
@@ -160,6 +161,7 @@ class Problem:
     scheme: int = SCHEME_CRKDG
     bc_upper: tuple = (0, 0, 0)   # upper side per direction; 0: as bc
     bc_state: dict = field(default_factory=dict)  # side 2 d + upper -> Dirichlet state
+    alpha: int = ALPHA_FACE
 
     def to_c(self) -> CProblem:
         p = CProblem()
@@ -173,7 +175,7 @@ class Problem:
         p.system, p.k, p.space, p.stages = self.system, self.k, self.space, self.stages
         p.precision, p.limiter, p.max_halvings = self.precision, int(self.limiter), self.max_halvings
         p.gamma, p.bound_lo, p.bound_hi = self.gamma, self.bound_lo, self.bound_hi
-        p.eps, p.cfl, p.scheme = self.eps, self.cfl, self.scheme
+        p.eps, p.cfl, p.scheme, p.alpha = self.eps, self.cfl, self.scheme, self.alpha
         for i in range(3):
             p.bc_upper[i] = int(self.bc_upper[i]) if i < len(self.bc_upper) else 0
         for side, vals in self.bc_state.items():
@@ -191,7 +193,7 @@ def problem_from_params(params: dict) -> Problem:
     """Problem from a workload parameter dict (names as in crkdg_problem,
     enumerations spelled as words: system 'euler', space 'Q', bc 'periodic',
     precision 'fp64' / 'mixed', scheme 'crkdg' / 'rkdg'; bc_upper per direction,
-    bc_state {side 2 d + upper: state})."""
+    bc_state {side 2 d + upper: state}; alpha 'face' / 'point')."""
     d = params["dim"]
     bc = tuple(_BC_NAMES[b] for b in params.get("bc", ("periodic",) * d)) + (BC_PERIODIC,) * (3 - d)
     n = tuple(params["n"]) + (1,) * (3 - d)
@@ -206,7 +208,8 @@ def problem_from_params(params: dict) -> Problem:
         cfl=params.get("cfl", 0.1), max_halvings=params.get("max_halvings", 40),
         scheme=_SCHEME_NAMES[params.get("scheme", "crkdg")],
         bc_upper=tuple(_BC_NAMES[b] for b in params["bc_upper"]) if params.get("bc_upper") else (0, 0, 0),
-        bc_state=dict(params.get("bc_state", {})))
+        bc_state=dict(params.get("bc_state", {})),
+        alpha=ALPHA_POINT if params.get("alpha", "face") == "point" else ALPHA_FACE)
 
 
 class State:

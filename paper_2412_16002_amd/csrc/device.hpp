@@ -40,6 +40,7 @@ struct InstDev {
   int32_t first_block;  // logical block range of this instance
   int32_t n_blocks;
   int32_t dim;
+  int32_t alpha_point;  // 1: Lax-Friedrichs alpha at each face point
   double rdx[3];     // 1 / dx_d
   double r2dx[3];    // 2 / dx_d
   double vel[3];
@@ -917,6 +918,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
       }
       // canonical orientation: L = lower cell, R = upper cell
       T fL[S::NFP][V], fR[S::NFP][V];
+      T sp[S::NFP];
       T alpha = T(0);
 #pragma unroll
       for (int b = 0; b < S::NFP; ++b) {
@@ -926,17 +928,18 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
         const auto aR = P::aux(uR, I);
         P::flux(uL, aL, d, I, fL[b]);
         P::flux(uR, aR, d, I, fR[b]);
-        alpha = fmax(alpha, fmax(P::speed(uL, aL, d, I), P::speed(uR, aR, d, I)));
+        sp[b] = fmax(P::speed(uL, aL, d, I), P::speed(uR, aR, d, I));
+        alpha = fmax(alpha, sp[b]);
       }
       T fn[S::NFP][V];
       {
         // same operations, in the same order, in both cells of the face
 #pragma clang fp contract(off)
-        const T ha = T(0.5) * alpha;
 #pragma unroll
         for (int b = 0; b < S::NFP; ++b) {
           const T* uL = upper ? ui[b] : ue[b];
           const T* uR = upper ? ue[b] : ui[b];
+          const T ha = T(0.5) * (I.alpha_point ? sp[b] : alpha);
 #pragma unroll
           for (int v = 0; v < V; ++v)
             fn[b][v] = fma(-ha, uR[v] - uL[v], T(0.5) * (fL[b][v] + fR[b][v]));

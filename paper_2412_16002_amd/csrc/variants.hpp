@@ -14,6 +14,7 @@ struct VariantOps {
   int M, V, NQ, NS;
   int rec_bytes;   // bytes of one deferred-limiter queue record
   int walls;       // reflective and Dirichlet sides built in
+  int alpha_point; // Lax-Friedrichs alpha per face point built in
   Launch stage_local, stage_final, limit, cfl, project, queue_local, queue_final;
   Launch stage_local_p, stage_final_p;   // persistent-grid forms
   Launch stage_inner_dg, stage_inner_dg_p; // inner stage with F (standard RKDG)
@@ -57,6 +58,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Ops {
   static VariantOps make() {
     return VariantOps{D, K, SP, SYS, sizeof(T) == 8 ? CRKDG_FP64 : CRKDG_MIXED,
                       C::M, C::V, C::S::NQ, C::NS, static_cast<int>(sizeof(typename C::Record)), C::WALLS ? 1 : 0,
+                      C::BIG ? 0 : 1,
                       &stage_local, &stage_final, &limit, &cfl, &project, &queue_local, &queue_final,
                       &stage_local_p, &stage_final_p, &stage_inner_dg, &stage_inner_dg_p};
   }

@@ -1,0 +1,167 @@
+"""The per-point Lax--Friedrichs alpha (local LF, alpha at each face point
+from its two traces) on the GPU against the oracle's per-point form: the
+final stage F from random limited states, steps through the device
+controller in FP64 and mixed precision, the bitwise identity with the
+per-face form where the two alphas agree, and the variant that does not
+build it."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from _helpers import gpu_problem, oracle_problem, parity_tolerance, random_state, rel_err_per_var, round_hi
+from test_gpu_parity import CASES, FP64_TOL
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2412_16002_amd import crkdg
+    return crkdg
+
+
+def _setup(lib, name, precision="fp64", alpha="point", **extra):
+    params = dict(CASES[name], precision=precision, alpha=alpha, **extra)
+    return params, oracle.CRKDG(oracle_problem(params)), lib.Mesh(gpu_problem(params))
+
+
+def _states(mesh, coeffs):
+    out = []
+    for c in coeffs:
+        st = mesh.new_state()
+        mesh.set_legendre(st, c)
+        out.append(st)
+    return out
+
+
+FINAL_CASES = ["euler2d_q1_outflow", "euler2d_q2", "euler2d_q3", "euler2d_p1", "euler2d_p2", "euler2d_p3",
+               "euler3d_q1", "euler3d_p1", "burgers1d_p2", "euler1d_p3_outflow"]
+
+
+@pytest.mark.parametrize("name", FINAL_CASES)
+def test_point_alpha_final_stage_parity(lib, name):
+    """The final stage (the one that applies F) from the same random limited
+    states, limited, element by element against the oracle."""
+    params, o, mesh = _setup(lib, name)
+    s = o.p.stages
+    tilde = [random_state(o, seed=120 + j, rel_amp=0.1) for j in range(s)]
+    U = [o.from_legendre(c) for c in tilde]
+    dt = 0.8 * o.trial_dt(U[0])
+    states = _states(mesh, tilde)
+    out = mesh.new_state()
+    ctl = mesh.new_ctl()
+    _say(f"[point alpha final] {name}")
+    ref_u = o.stage(s + 1, U[0], U, dt)
+    ok_ref = bool(np.all(o.admissible_average(o.cell_average(ref_u))))
+    ref = o.to_legendre(o.limit(ref_u)[0])
+    mesh.ctl_write(ctl, [{"dt": dt}])
+    mesh.stage(s + 1, states, out, ctl)
+    got = mesh.get_legendre(out)
+    c = mesh.ctl_read(ctl)[0]
+    err = float(np.max(np.abs(got - ref) / parity_tolerance(o, o.to_legendre(ref_u), ref, FP64_TOL)))
+    _say(f"   error/tolerance {err:.2e} flags {c['flags']} oracle-admissible {ok_ref}")
+    assert (c["flags"] == 0) == ok_ref
+    assert err < 1.0
+    if o.d > 1 and o.p.system != oracle.ADVECTION:
+        # the option takes effect: the per-face form gives another stage
+        _, _, mf = _setup(lib, name, alpha="face")
+        sf = _states(mf, tilde)
+        of = mf.new_state()
+        cf = mf.new_ctl()
+        mf.ctl_write(cf, [{"dt": dt}])
+        mf.stage(s + 1, sf, of, cf)
+        assert np.max(np.abs(mf.get_legendre(of) - got)) > 1e-8 * np.max(np.abs(got))
+
+
+@pytest.mark.parametrize("name,precision", [("euler2d_q2", "fp64"), ("euler2d_p3", "fp64"), ("euler3d_q1", "fp64"),
+                                            ("euler2d_q2", "mixed"), ("euler2d_p2", "mixed")])
+def test_point_alpha_step_parity(lib, name, precision):
+    """Three accepted steps through the device controller against the
+    oracle's steps with the per-point alpha (FP64: 10x the stage tolerance;
+    mixed: 1e-5 of the variable's magnitude)."""
+    params, o, mesh = _setup(lib, name, precision=precision)
+    C0 = round_hi(random_state(o, seed=131, rel_amp=0.1), precision)
+    slots = mesh.new_slots()
+    mesh.set_legendre(slots[0], C0)
+    ctl = mesh.new_ctl()
+    mesh.start(slots, ctl, t0=0.0)
+    U = o.from_legendre(C0)
+    t = 0.0
+    T0 = mesh.totals(slots[0]).cpu().numpy().copy()
+    for n in range(3):
+        _say(f"[point alpha step] {name} {precision} step {n}")
+        U, info_o = o.step(U, t)
+        t = info_o["t"]
+        info = mesh.step(slots, ctl)[0]
+        assert info["status"] == 0 and info["halvings"] == info_o["halvings"]
+        assert math.isclose(info["dt"], info_o["dt"], rel_tol=1e-12 if precision == "fp64" else 1e-5)
+        got = mesh.get_legendre(slots[info["cur"]])
+        err = rel_err_per_var(got, o.to_legendre(U))
+        _say(f"   dt {info['dt']:.4e} rel err {err:.2e}")
+        assert err < (10 * FP64_TOL if precision == "fp64" else 1e-5)
+        assert o.bound_violations(o.from_legendre(got)) == 0
+    T = mesh.totals(slots[info["cur"]]).cpu().numpy()
+    assert np.all(np.abs(T - T0) <= 1e-13 * np.maximum(np.abs(T0), 1.0))
+
+
+@pytest.mark.parametrize("name", ["adv2d_q2", "adv3d_q2", "euler1d_p1"])
+def test_point_alpha_bitwise_where_alphas_agree(lib, name):
+    """Constant wave speed (advection) or one point per face (1D): the two
+    forms take the same alpha everywhere, and the steps agree bit for bit."""
+    out = {}
+    for alpha in ("face", "point"):
+        params, o, mesh = _setup(lib, name, alpha=alpha)
+        C0 = random_state(o, seed=141, rel_amp=0.1)
+        slots = mesh.new_slots()
+        mesh.set_legendre(slots[0], C0)
+        ctl = mesh.new_ctl()
+        mesh.start(slots, ctl)
+        for _ in range(2):
+            info = mesh.step(slots, ctl)[0]
+        out[alpha] = mesh.get_legendre(slots[info["cur"]])
+    assert np.array_equal(out["face"], out["point"])
+
+
+def test_point_alpha_batch_with_both_forms(lib):
+    """A batch holding one problem under both alphas steps each instance
+    bitwise as it steps alone (the alpha is per instance, not per kernel)."""
+    name = "euler2d_p2"
+    solo = {}
+    for alpha in ("face", "point"):
+        params, o, mesh = _setup(lib, name, alpha=alpha)
+        C0 = random_state(o, seed=151, rel_amp=0.1)
+        slots = mesh.new_slots()
+        mesh.set_legendre(slots[0], C0)
+        ctl = mesh.new_ctl()
+        mesh.start(slots, ctl)
+        infos = [mesh.step(slots, ctl)[0] for _ in range(2)]
+        solo[alpha] = (infos[-1], mesh.get_legendre(slots[infos[-1]["cur"]]))
+    both = lib.Mesh([gpu_problem(dict(CASES[name], precision="fp64", alpha=a)) for a in ("face", "point")])
+    slots = both.new_slots()
+    for i in range(2):
+        both.set_legendre(slots[0], C0, inst=i)
+    ctl = both.new_ctl()
+    both.start(slots, ctl)
+    for _ in range(2):
+        infos = both.step(slots, ctl)
+    for i, alpha in enumerate(("face", "point")):
+        assert infos[i]["dt"] == solo[alpha][0]["dt"]
+        assert np.array_equal(both.get_legendre(slots[infos[i]["cur"]], inst=i), solo[alpha][1])
+
+
+def test_point_alpha_not_built_for_3d_q2_euler(lib):
+    """3D Q^2 Euler keeps only the per-face alpha (its face loop runs at the
+    register limit); asking for the per-point form fails at init."""
+    with pytest.raises(lib.CRKDGError) as e:
+        lib.Mesh(gpu_problem(dict(CASES["euler3d_q2"], precision="fp64", alpha="point")))
+    assert e.value.code == lib.E_UNSUPPORTED
