@@ -41,7 +41,10 @@ design notes of the repository):
       Optional (Problem.alpha = "point"): alpha at each face quadrature point
       from its two traces alone (local LF); Prop. 2.1's bound argument holds
       pointwise, since each point's alpha still bounds the wave speed of both
-      of its traces.
+      of its traces.  Optional (Problem.alpha = "global"): one alpha for every
+      face of every stage of a step, the a0 of Sec. 2.1 taken as the maximum
+      over directions of a0_d(u~^n) (A5); stage values whose wave speeds
+      exceed it are caught by the average check and halving (A10).
   A2  multi-D trial step: dt = CFL / sum_d (a0_d / dx_d)  (1D: CFL dx / a0).
   A4  S_K = union over d of (Gauss^{k+1} in the other directions x
       Gauss--Lobatto^N in direction d), N = 2 for k = 1, N = 3 for k = 2, 3.
@@ -198,7 +201,7 @@ class Problem:
     cfl: float = 0.1
     max_halvings: int = 40
     limiter: bool = True
-    alpha: str = "face"           # LF alpha per face (A1) or per face point
+    alpha: str = "face"           # LF alpha per face (A1), per face point, or global
 
     @property
     def nvars(self):
@@ -233,8 +236,8 @@ class CRKDG:
         self.vol = float(np.prod(self.dx))
         if prob.space not in ("P", "Q"):
             raise ValueError("space must be P or Q")
-        if prob.alpha not in ("face", "point"):
-            raise ValueError("alpha must be face or point")
+        if prob.alpha not in ("face", "point", "global"):
+            raise ValueError("alpha must be face, point or global")
         self.space = "Q" if d == 1 else prob.space
         for dd in range(d):
             kinds = (prob.side_bc(dd, -1), prob.side_bc(dd, 1))
@@ -485,13 +488,18 @@ class CRKDG:
             r -= self._face_residual(face, face["side"] * self.flux(uf, face["dim"]))
         return np.linalg.solve(self.mass, r.reshape(-1, self.M).T).T.reshape(r.shape)
 
-    def lf_flux(self, um, up, dd, side):
+    def lf_flux(self, um, up, dd, side, a_glob=None):
         """Lax--Friedrichs flux f^.nu on a face with outward normal side*e_dd
         (Sec. 2.1); um/up [c, b, V] interior/exterior traces.  alpha per face
-        (reading A1) or, with alpha = "point", per face point."""
+        (reading A1), per face point (alpha = "point"), or the given a_glob
+        (alpha = "global")."""
         a = np.maximum(self.wave_speed(um, dd), self.wave_speed(up, dd))     # [c, b]
         if self.p.alpha == "face":
             a = np.broadcast_to(a.max(axis=1)[:, None], a.shape)
+        elif self.p.alpha == "global":
+            if a_glob is None:
+                raise ValueError("the global alpha needs a_glob")
+            a = np.full(a.shape, float(a_glob))
         return (0.5 * side * (self.flux(um, dd) + self.flux(up, dd))
                 - 0.5 * a[:, :, None] * (up - um))
 
@@ -513,13 +521,14 @@ class CRKDG:
             up[inner] = np.einsum("cvm,bm->cbv", U[nb[inner]], opp["phi"])
         return um, up
 
-    def F(self, U, cells=None):
-        """DG operator F = -div^DG f with the Lax--Friedrichs flux (Sec. 2.1)."""
+    def F(self, U, cells=None, a_glob=None):
+        """DG operator F = -div^DG f with the Lax--Friedrichs flux (Sec. 2.1);
+        a_glob is the alpha of every face when Problem.alpha is "global"."""
         cells = np.arange(self.ncell) if cells is None else np.asarray(cells)
         r = self._volume_residual(U[cells])
         for face in self.faces:
             um, up = self.face_traces(U, cells, face)
-            r -= self._face_residual(face, self.lf_flux(um, up, face["dim"], face["side"]))
+            r -= self._face_residual(face, self.lf_flux(um, up, face["dim"], face["side"], a_glob))
         return np.linalg.solve(self.mass, r.reshape(-1, self.M).T).T.reshape(r.shape)
 
     # ---------------- admissibility and limiter (Sec. 2.2) ----------------
@@ -614,15 +623,21 @@ class CRKDG:
         A, b = BUTCHER[self.p.stages]
         s = self.p.stages
         out = Un.copy()
+        F = self.F
+        if self.p.alpha == "global":                     # a0 of u~^n (A1 option)
+            ag = float(np.max(self.a0(Un)))
+
+            def F(V):
+                return self.F(V, a_glob=ag)
         if i <= s:
-            inner = self.G if op is None else op
+            inner = self.G if op is None else (F if op == self.F else op)
             for j in range(1, i):
                 if A[i - 1, j - 1] != 0.0:
                     out = out + dt * A[i - 1, j - 1] * inner(tilde[j - 1])
         else:
             for j in range(1, s + 1):
                 if b[j - 1] != 0.0:
-                    out = out + dt * b[j - 1] * self.F(tilde[j - 1])
+                    out = out + dt * b[j - 1] * F(tilde[j - 1])
         return out
 
     def attempt(self, Un, dt, op=None):

@@ -139,3 +139,81 @@ def test_point_alpha_density_wave_converges():
             t = info["t"]
         errs.append(o.l1_norm(U, lambda X: case.exact(X, T))[0])
     assert math.log2(errs[0] / errs[1]) > k + 1 - 0.3, errs
+
+
+# ---------------- the global alpha (the a0 of Sec. 2.1) ----------------
+def test_global_alpha_needs_its_value():
+    o = CRKDG(Problem(dim=1, n=(8,), system=ADVECTION, alpha="global"))
+    U = o.project(lambda X: np.sin(2 * np.pi * X[..., :1]) + 2.0)
+    with pytest.raises(ValueError):
+        o.F(U)
+
+
+@pytest.mark.parametrize("vel", [(1.0, -1.0, 0.0), (0.6, 0.6, 0.0)])
+def test_global_alpha_equals_per_face_when_every_face_has_a0(vel):
+    """Advection with |a_x| = |a_y|: every face's alpha is a0, so the global
+    and the per-face schemes agree bit for bit."""
+    of = CRKDG(Problem(dim=2, n=(7, 6), system=ADVECTION, k=2, stages=3, vel=vel))
+    og = CRKDG(Problem(dim=2, n=(7, 6), system=ADVECTION, k=2, stages=3, vel=vel, alpha="global"))
+    U = _rough(of, 61)
+    assert float(np.max(og.a0(U))) == abs(vel[0])
+    assert np.array_equal(_steps(of, U, 2), _steps(og, U, 2))
+
+
+def test_global_alpha_differs_where_speeds_differ():
+    """Advection with a = (1, 0.25): the global alpha (a0 = 1) puts 4x the
+    per-face dissipation on the y-faces, and the two schemes differ."""
+    vel = (1.0, 0.25, 0.0)
+    of = CRKDG(Problem(dim=2, n=(6, 5), system=ADVECTION, k=2, stages=3, vel=vel))
+    og = CRKDG(Problem(dim=2, n=(6, 5), system=ADVECTION, k=2, stages=3, vel=vel, alpha="global"))
+    U = _rough(of, 71)
+    assert float(np.max(og.a0(U))) == 1.0
+    Ff, Fg = of.F(U), og.F(U, a_glob=1.0)
+    assert np.max(np.abs(Ff - Fg)) > 1e-6 * np.max(np.abs(Fg))
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_global_alpha_no_rejection_under_theoretical_cfl(k):
+    """Thm. 3.5 is stated with the global a0: 2D Burgers, rough admissible
+    data, 0.9 of its CFL: no halving, no violation, with the global alpha."""
+    from test_oracle_method import GOLDEN
+    s = k + 1
+    lo_b, hi_b = 0.2, 1.1
+    mu = GOLDEN["rk_objective"][str(s)]
+    c = 0.5 if k == 1 else 1.0 / 6.0
+    o = CRKDG(Problem(dim=2, n=(16, 16), system=BURGERS, k=k, stages=s, bound_lo=lo_b, bound_hi=hi_b,
+                      alpha="global"))
+    rng = np.random.default_rng(80 + k)
+    avg = rng.uniform(lo_b, hi_b, (o.ncell, 1))
+    C = inputs.random_legendre(o.ncell, 1, o.M, [sum(e) for e in o.legendre_modes()], seed=81, avg=avg,
+                               rel_amp=3.0)
+    U = o.limit(o.from_legendre(C))[0]
+    a0 = max(abs(lo_b), abs(hi_b))
+    dt = 0.9 * c / mu / (a0 / o.dx[0] + a0 / o.dx[1])
+    for _ in range(6):
+        U, info = o.step(U, dt_fixed=dt)
+        assert info["halvings"] == 0
+        assert o.bound_violations(U) == 0
+
+
+def test_global_alpha_conserves_and_converges():
+    """Conservation on rough 2D Euler data, and order k+1 on the diagonal
+    density wave with the global alpha."""
+    o = CRKDG(Problem(dim=2, n=(10, 10), system=EULER, k=2, stages=3, cfl=0.1, alpha="global"))
+    U = _rough(o, 91)
+    T0 = o.totals(U)
+    U1 = _steps(o, U, 3)
+    assert np.all(np.abs(o.totals(U1) - T0) <= 1e-14 * np.abs(T0) * o.ncell ** 0.5 + 1e-15)
+    assert o.bound_violations(U1) == 0
+    k = 2
+    errs = []
+    for N in (16, 32):       # measured: 2.59 from 8 to 16 (pre-asymptotic), 2.93 from 16 to 32
+        case = inputs.euler_wave(2, (N, N), k, amp=0.5)
+        o = CRKDG(Problem(dim=2, n=(N, N), system=EULER, k=k, stages=3, cfl=0.1, alpha="global"))
+        U = o.limit(o.project(case.u0))[0]
+        t, T = 0.0, 0.05
+        while t < T:
+            U, info = o.step(U, t, T)
+            t = info["t"]
+        errs.append(o.l1_norm(U, lambda X: case.exact(X, T))[0])
+    assert math.log2(errs[0] / errs[1]) > k + 1 - 0.3, errs
