@@ -87,8 +87,12 @@ extern "C" {
                                quadrature points and both traces (the reading of Sec. 2.1 used
                                throughout) */
 #define CRKDG_ALPHA_POINT 1 /* alpha at each face quadrature point from its two traces (local
-                               Lax-Friedrichs / Rusanov); not built for 3D Q^2 Euler, whose
-                               init call returns CRKDG_E_UNSUPPORTED */
+                               Lax-Friedrichs / Rusanov) */
+#define CRKDG_ALPHA_GLOBAL 2 /* one alpha for every face: the wave-speed maximum a0 of Sec. 2.1,
+                               max over d of crkdg_ctl.a0[d] (that of u~^n over S_K, which the
+                               controller holds during a step; a caller of crkdg_stage sets it).
+                               Neither option is built for 3D Q^2 Euler, whose init call returns
+                               CRKDG_E_UNSUPPORTED */
 
 #define CRKDG_FP64 0  /* every mode and all arithmetic in FP64 */
 #define CRKDG_MIXED 1 /* modes >= 1 and transforms/fluxes in FP32; averages,

@@ -22,7 +22,7 @@ SYS_ADVECTION, SYS_BURGERS, SYS_EULER = 0, 1, 2
 SPACE_Q, SPACE_P = 0, 1
 FP64, MIXED = 0, 1
 SCHEME_CRKDG, SCHEME_RKDG = 0, 1
-ALPHA_FACE, ALPHA_POINT = 0, 1
+ALPHA_FACE, ALPHA_POINT, ALPHA_GLOBAL = 0, 1, 2
 E_ARG, E_HIP, E_UNSUPPORTED, E_LAYOUT = -1, -2, -3, -4
 S_REJECTED, S_DT_UNDERFLOW, S_NONFINITE, S_DONE = 1, 2, 3, 4
 F_AVERAGE, F_NONFINITE = 1, 2
@@ -193,7 +193,7 @@ def problem_from_params(params: dict) -> Problem:
     """Problem from a workload parameter dict (names as in crkdg_problem,
     enumerations spelled as words: system 'euler', space 'Q', bc 'periodic',
     precision 'fp64' / 'mixed', scheme 'crkdg' / 'rkdg'; bc_upper per direction,
-    bc_state {side 2 d + upper: state}; alpha 'face' / 'point')."""
+    bc_state {side 2 d + upper: state}; alpha 'face' / 'point' / 'global')."""
     d = params["dim"]
     bc = tuple(_BC_NAMES[b] for b in params.get("bc", ("periodic",) * d)) + (BC_PERIODIC,) * (3 - d)
     n = tuple(params["n"]) + (1,) * (3 - d)
@@ -209,7 +209,7 @@ def problem_from_params(params: dict) -> Problem:
         scheme=_SCHEME_NAMES[params.get("scheme", "crkdg")],
         bc_upper=tuple(_BC_NAMES[b] for b in params["bc_upper"]) if params.get("bc_upper") else (0, 0, 0),
         bc_state=dict(params.get("bc_state", {})),
-        alpha=ALPHA_POINT if params.get("alpha", "face") == "point" else ALPHA_FACE)
+        alpha={"face": ALPHA_FACE, "point": ALPHA_POINT, "global": ALPHA_GLOBAL}[params.get("alpha", "face")])
 
 
 class State:

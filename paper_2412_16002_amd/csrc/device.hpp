@@ -40,7 +40,7 @@ struct InstDev {
   int32_t first_block;  // logical block range of this instance
   int32_t n_blocks;
   int32_t dim;
-  int32_t alpha_point;  // 1: Lax-Friedrichs alpha at each face point
+  int32_t alpha_mode;   // CRKDG_ALPHA_*: Lax-Friedrichs alpha per face, per point, global
   double rdx[3];     // 1 / dx_d
   double r2dx[3];    // 2 / dx_d
   double vel[3];
@@ -881,12 +881,23 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
   // formed in the canonical (lower cell, upper cell) orientation with the same
   // operation order in both cells, so the two cells of a face see bitwise the
   // same value and the averages are updated conservatively.
+  // The global Lax-Friedrichs alpha: the wave-speed maximum a0 of u~^n over
+  // S_K and all directions (Sec. 2.1), as the controller holds it in a step.
+  __device__ __forceinline__ static double global_alpha(const crkdg_ctl* ctl) {
+    double a = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) a = fmax(a, ctl->a0[d]);
+    return a;
+  }
+
+  // `ag` is the global alpha (used when I.alpha_mode is CRKDG_ALPHA_GLOBAL).
   __device__ __forceinline__ static void op_dg(const State& s, const double* avg, const T* hi,
-                                               const CellPos& p, const InstDev& I, double scale, Acc& r) {
+                                               const CellPos& p, const InstDev& I, double scale, Acc& r,
+                                               double ag) {
     if constexpr (BIG) {
       op_dg_big(s, avg, hi, p, I, scale, r);
     } else {
-      op_dg_from(s, p, I, scale, r,
+      op_dg_from(s, p, I, scale, r, ag,
                  [&](int, int64_t nb, State& sn) { load(avg, hi, I.ncell, nb, sn); });
     }
   }
@@ -894,7 +905,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
   // F with the neighbour states read by getnb(f, nb, state)
   template <class GetNb>
   __device__ __forceinline__ static void op_dg_from(const State& s, const CellPos& p, const InstDev& I,
-                                                    double scale, Acc& r, GetNb getnb) {
+                                                    double scale, Acc& r, double ag, GetNb getnb) {
     volume(s, I, scale, r);
 #pragma unroll
     for (int f = 0; f < S::NF; ++f) {
@@ -931,6 +942,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
         sp[b] = fmax(P::speed(uL, aL, d, I), P::speed(uR, aR, d, I));
         alpha = fmax(alpha, sp[b]);
       }
+      if (I.alpha_mode == CRKDG_ALPHA_GLOBAL) alpha = static_cast<T>(ag);
       T fn[S::NFP][V];
       {
         // same operations, in the same order, in both cells of the face
@@ -939,7 +951,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
         for (int b = 0; b < S::NFP; ++b) {
           const T* uL = upper ? ui[b] : ue[b];
           const T* uR = upper ? ue[b] : ui[b];
-          const T ha = T(0.5) * (I.alpha_point ? sp[b] : alpha);
+          const T ha = T(0.5) * (I.alpha_mode == CRKDG_ALPHA_POINT ? sp[b] : alpha);
 #pragma unroll
           for (int v = 0; v < V; ++v)
             fn[b][v] = fma(-ha, uR[v] - uL[v], T(0.5) * (fL[b][v] + fR[b][v]));
@@ -1338,7 +1350,7 @@ __device__ __forceinline__ void stage_local_item(const KArgs& a, const BlockItem
     typename C::Acc r;
     C::zero(r);
     if constexpr (DG)
-      C::op_dg(u, in_avg, in_hi, pos, I, dt * a.a, r);
+      C::op_dg(u, in_avg, in_hi, pos, I, dt * a.a, r, C::global_alpha(ctl));
     else
       C::op_local(u, I, dt * a.a, r);
     typename C::State base, out;
@@ -1416,7 +1428,7 @@ __device__ __forceinline__ void stage_final_item(const KArgs& a, const BlockItem
       const T* j_hi = hi_ptr<T>(sel_hi(a.slots, sl), I.hi_off);
       typename C::State uj;
       C::load(j_avg, j_hi, I.ncell, c, uj);
-      C::op_dg(uj, j_avg, j_hi, pos, I, dt * a.b[j - 1], r);
+      C::op_dg(uj, j_avg, j_hi, pos, I, dt * a.b[j - 1], r, C::global_alpha(ctl));
     }
     typename C::State base;
     C::load(b_avg, b_hi, I.ncell, c, base);

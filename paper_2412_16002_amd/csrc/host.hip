@@ -216,7 +216,8 @@ int validate(const crkdg_problem& p, int idx) {
   if (!(p.cfl > 0.0)) return bad("cfl must be positive");
   if (p.max_halvings < 0) return bad("max_halvings must be >= 0");
   if (p.scheme != CRKDG_SCHEME_CRKDG && p.scheme != CRKDG_SCHEME_RKDG) return bad("unknown scheme");
-  if (p.alpha != CRKDG_ALPHA_FACE && p.alpha != CRKDG_ALPHA_POINT) return bad("unknown alpha");
+  if (p.alpha != CRKDG_ALPHA_FACE && p.alpha != CRKDG_ALPHA_POINT && p.alpha != CRKDG_ALPHA_GLOBAL)
+    return bad("unknown alpha");
   int64_t nc = 1;
   for (int d = 0; d < p.dim; ++d) nc *= p.n[d];
   if (nc > INT32_MAX) return bad("more than 2^31 - 1 cells in one instance");
@@ -463,11 +464,11 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
                                                  ": reflective and Dirichlet sides are not built for this "
                                                  "dim/k/space/system/precision (2D Q^3 Euler FP64)");
           }
-    if (!ops->alpha_point && p.alpha == CRKDG_ALPHA_POINT) {
+    if (!ops->alpha_modes && p.alpha != CRKDG_ALPHA_FACE) {
       delete m;
       return fail(CRKDG_E_UNSUPPORTED, "problem " + std::to_string(i) +
-                                           ": the per-point Lax-Friedrichs alpha is not built for this "
-                                           "dim/k/space/system (3D Q^2 Euler)");
+                                           ": the per-point and global Lax-Friedrichs alpha are not built "
+                                           "for this dim/k/space/system (3D Q^2 Euler)");
     }
     int64_t nc = 1;
     for (int d = 0; d < p.dim; ++d) nc *= p.n[d];
@@ -510,7 +511,7 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
     I.dim = p.dim;
     I.stages = p.stages;
     I.limiter = p.limiter;
-    I.alpha_point = (p.alpha == CRKDG_ALPHA_POINT) ? 1 : 0;
+    I.alpha_mode = p.alpha;
     I.max_halvings = p.max_halvings;
     I.gamma = p.gamma;
     I.blo = p.bound_lo;

@@ -14,7 +14,7 @@ struct VariantOps {
   int M, V, NQ, NS;
   int rec_bytes;   // bytes of one deferred-limiter queue record
   int walls;       // reflective and Dirichlet sides built in
-  int alpha_point; // Lax-Friedrichs alpha per face point built in
+  int alpha_modes; // per-point and global Lax-Friedrichs alpha built in
   Launch stage_local, stage_final, limit, cfl, project, queue_local, queue_final;
   Launch stage_local_p, stage_final_p;   // persistent-grid forms
   Launch stage_inner_dg, stage_inner_dg_p; // inner stage with F (standard RKDG)

@@ -1,9 +1,10 @@
 """The per-point Lax--Friedrichs alpha (local LF, alpha at each face point
-from its two traces) on the GPU against the oracle's per-point form: the
-final stage F from random limited states, steps through the device
-controller in FP64 and mixed precision, the bitwise identity with the
-per-face form where the two alphas agree, and the variant that does not
-build it."""
+from its two traces) and the global one (the a0 of u~^n over S_K) on the GPU
+against the oracle's same forms: the final stage F from random limited
+states, steps through the device controller in FP64 and mixed precision
+(and standard RKDG with the global alpha), the bitwise identity with the
+per-face form where the alphas agree, and the variant that does not build
+them."""
 import math
 import sys
 
@@ -48,11 +49,13 @@ FINAL_CASES = ["euler2d_q1_outflow", "euler2d_q2", "euler2d_q3", "euler2d_p1", "
                "euler3d_q1", "euler3d_p1", "burgers1d_p2", "euler1d_p3_outflow"]
 
 
+@pytest.mark.parametrize("alpha", ["point", "global"])
 @pytest.mark.parametrize("name", FINAL_CASES)
-def test_point_alpha_final_stage_parity(lib, name):
+def test_alpha_final_stage_parity(lib, name, alpha):
     """The final stage (the one that applies F) from the same random limited
-    states, limited, element by element against the oracle."""
-    params, o, mesh = _setup(lib, name)
+    states, limited, element by element against the oracle; for the global
+    alpha the controller record carries the oracle's a0 of u~^n."""
+    params, o, mesh = _setup(lib, name, alpha=alpha)
     s = o.p.stages
     tilde = [random_state(o, seed=120 + j, rel_amp=0.1) for j in range(s)]
     U = [o.from_legendre(c) for c in tilde]
@@ -60,11 +63,12 @@ def test_point_alpha_final_stage_parity(lib, name):
     states = _states(mesh, tilde)
     out = mesh.new_state()
     ctl = mesh.new_ctl()
-    _say(f"[point alpha final] {name}")
+    _say(f"[{alpha} alpha final] {name}")
     ref_u = o.stage(s + 1, U[0], U, dt)
     ok_ref = bool(np.all(o.admissible_average(o.cell_average(ref_u))))
     ref = o.to_legendre(o.limit(ref_u)[0])
-    mesh.ctl_write(ctl, [{"dt": dt}])
+    rec = {"dt": dt, "a0": [float(x) for x in o.a0(U[0])]}
+    mesh.ctl_write(ctl, [rec])
     mesh.stage(s + 1, states, out, ctl)
     got = mesh.get_legendre(out)
     c = mesh.ctl_read(ctl)[0]
@@ -78,18 +82,22 @@ def test_point_alpha_final_stage_parity(lib, name):
         sf = _states(mf, tilde)
         of = mf.new_state()
         cf = mf.new_ctl()
-        mf.ctl_write(cf, [{"dt": dt}])
+        mf.ctl_write(cf, [rec])
         mf.stage(s + 1, sf, of, cf)
         assert np.max(np.abs(mf.get_legendre(of) - got)) > 1e-8 * np.max(np.abs(got))
 
 
-@pytest.mark.parametrize("name,precision", [("euler2d_q2", "fp64"), ("euler2d_p3", "fp64"), ("euler3d_q1", "fp64"),
-                                            ("euler2d_q2", "mixed"), ("euler2d_p2", "mixed")])
-def test_point_alpha_step_parity(lib, name, precision):
+@pytest.mark.parametrize("name,precision,alpha,scheme", [
+    ("euler2d_q2", "fp64", "point", "crkdg"), ("euler2d_p3", "fp64", "point", "crkdg"),
+    ("euler3d_q1", "fp64", "point", "crkdg"), ("euler2d_q2", "mixed", "point", "crkdg"),
+    ("euler2d_p2", "mixed", "point", "crkdg"), ("euler2d_q2", "fp64", "global", "crkdg"),
+    ("euler3d_p1", "fp64", "global", "crkdg"), ("euler2d_q2", "fp64", "global", "rkdg"),
+    ("euler2d_p2", "mixed", "global", "crkdg")])
+def test_alpha_step_parity(lib, name, precision, alpha, scheme):
     """Three accepted steps through the device controller against the
-    oracle's steps with the per-point alpha (FP64: 10x the stage tolerance;
+    oracle's steps with the same alpha (FP64: 10x the stage tolerance;
     mixed: 1e-5 of the variable's magnitude)."""
-    params, o, mesh = _setup(lib, name, precision=precision)
+    params, o, mesh = _setup(lib, name, precision=precision, alpha=alpha, scheme=scheme)
     C0 = round_hi(random_state(o, seed=131, rel_amp=0.1), precision)
     slots = mesh.new_slots()
     mesh.set_legendre(slots[0], C0)
@@ -99,8 +107,8 @@ def test_point_alpha_step_parity(lib, name, precision):
     t = 0.0
     T0 = mesh.totals(slots[0]).cpu().numpy().copy()
     for n in range(3):
-        _say(f"[point alpha step] {name} {precision} step {n}")
-        U, info_o = o.step(U, t)
+        _say(f"[{alpha} alpha step] {name} {precision} {scheme} step {n}")
+        U, info_o = o.step(U, t, op=o.F if scheme == "rkdg" else None)
         t = info_o["t"]
         info = mesh.step(slots, ctl)[0]
         assert info["status"] == 0 and info["halvings"] == info_o["halvings"]
@@ -114,13 +122,16 @@ def test_point_alpha_step_parity(lib, name, precision):
     assert np.all(np.abs(T - T0) <= 1e-13 * np.maximum(np.abs(T0), 1.0))
 
 
-@pytest.mark.parametrize("name", ["adv2d_q2", "adv3d_q2", "euler1d_p1"])
-def test_point_alpha_bitwise_where_alphas_agree(lib, name):
-    """Constant wave speed (advection) or one point per face (1D): the two
-    forms take the same alpha everywhere, and the steps agree bit for bit."""
+@pytest.mark.parametrize("name,forms", [("adv2d_q2", ("face", "point")), ("adv3d_q2", ("face", "point")),
+                                        ("euler1d_p1", ("face", "point")), ("adv2d_q2", ("face", "global"))])
+def test_alpha_bitwise_where_alphas_agree(lib, name, forms):
+    """Constant wave speed (advection) or one point per face (1D): the
+    per-face and per-point forms take the same alpha everywhere; with
+    |a_x| = |a_y| every face's alpha is also the global a0.  The steps
+    agree bit for bit."""
     out = {}
-    for alpha in ("face", "point"):
-        params, o, mesh = _setup(lib, name, alpha=alpha)
+    for alpha in forms:
+        params, o, mesh = _setup(lib, name, alpha=alpha, vel=(1.0, -1.0, 0.0))
         C0 = random_state(o, seed=141, rel_amp=0.1)
         slots = mesh.new_slots()
         mesh.set_legendre(slots[0], C0)
@@ -129,7 +140,7 @@ def test_point_alpha_bitwise_where_alphas_agree(lib, name):
         for _ in range(2):
             info = mesh.step(slots, ctl)[0]
         out[alpha] = mesh.get_legendre(slots[info["cur"]])
-    assert np.array_equal(out["face"], out["point"])
+    assert np.array_equal(out[forms[0]], out[forms[1]])
 
 
 def test_point_alpha_batch_with_both_forms(lib):
@@ -159,9 +170,10 @@ def test_point_alpha_batch_with_both_forms(lib):
         assert np.array_equal(both.get_legendre(slots[infos[i]["cur"]], inst=i), solo[alpha][1])
 
 
-def test_point_alpha_not_built_for_3d_q2_euler(lib):
+@pytest.mark.parametrize("alpha", ["point", "global"])
+def test_alpha_options_not_built_for_3d_q2_euler(lib, alpha):
     """3D Q^2 Euler keeps only the per-face alpha (its face loop runs at the
-    register limit); asking for the per-point form fails at init."""
+    register limit); asking for another form fails at init."""
     with pytest.raises(lib.CRKDGError) as e:
-        lib.Mesh(gpu_problem(dict(CASES["euler3d_q2"], precision="fp64", alpha="point")))
+        lib.Mesh(gpu_problem(dict(CASES["euler3d_q2"], precision="fp64", alpha=alpha)))
     assert e.value.code == lib.E_UNSUPPORTED

@@ -91,7 +91,7 @@ def test_init_rejects_bad_problems_without_gpu():
     p = crkdg.Problem(dim=1, n=(4,), scheme=7).to_c()
     assert crkdg.LIB.crkdg_init_mesh(ctypes.byref(p), 1, ctypes.byref(h), ctypes.byref(lay)) == crkdg.E_ARG
     assert b"scheme" in crkdg.LIB.crkdg_last_error()
-    p = crkdg.Problem(dim=1, n=(4,), alpha=2).to_c()
+    p = crkdg.Problem(dim=1, n=(4,), alpha=3).to_c()
     assert crkdg.LIB.crkdg_init_mesh(ctypes.byref(p), 1, ctypes.byref(h), ctypes.byref(lay)) == crkdg.E_ARG
     assert b"alpha" in crkdg.LIB.crkdg_last_error()
 
