@@ -308,6 +308,10 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
   // is never reached on periodic meshes; there only periodic and outflow
   // sides are accepted.
   static constexpr bool WALLS = BIG || MIXED || M * V <= 60;
+  // The per-point and global Lax-Friedrichs alpha: not in the BIG face loop,
+  // whose per-point pass runs at the register limit, nor in the 2D P^3 Euler
+  // FP64 kernels, where the option code alone makes them spill.
+  static constexpr bool ALPHA_MODES = !BIG && (MIXED || !(D == 2 && SP == CRKDG_SPACE_P && K == 3 && SYS == SYS_EULER));
 
   struct State {
     double ub[V];     // cell averages (FP64)
@@ -929,7 +933,6 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
       }
       // canonical orientation: L = lower cell, R = upper cell
       T fL[S::NFP][V], fR[S::NFP][V];
-      T sp[S::NFP];
       T alpha = T(0);
 #pragma unroll
       for (int b = 0; b < S::NFP; ++b) {
@@ -939,10 +942,10 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
         const auto aR = P::aux(uR, I);
         P::flux(uL, aL, d, I, fL[b]);
         P::flux(uR, aR, d, I, fR[b]);
-        sp[b] = fmax(P::speed(uL, aL, d, I), P::speed(uR, aR, d, I));
-        alpha = fmax(alpha, sp[b]);
+        alpha = fmax(alpha, fmax(P::speed(uL, aL, d, I), P::speed(uR, aR, d, I)));
       }
-      if (I.alpha_mode == CRKDG_ALPHA_GLOBAL) alpha = static_cast<T>(ag);
+      if constexpr (ALPHA_MODES)
+        if (I.alpha_mode == CRKDG_ALPHA_GLOBAL) alpha = static_cast<T>(ag);
       T fn[S::NFP][V];
       {
         // same operations, in the same order, in both cells of the face
@@ -951,7 +954,13 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
         for (int b = 0; b < S::NFP; ++b) {
           const T* uL = upper ? ui[b] : ue[b];
           const T* uR = upper ? ue[b] : ui[b];
-          const T ha = T(0.5) * (I.alpha_mode == CRKDG_ALPHA_POINT ? sp[b] : alpha);
+          T ab = alpha;
+          if (ALPHA_MODES && I.alpha_mode == CRKDG_ALPHA_POINT) {
+            // the point's own speed, recomputed so that the per-face form
+            // keeps no per-point values alive
+            ab = fmax(P::speed(uL, P::aux(uL, I), d, I), P::speed(uR, P::aux(uR, I), d, I));
+          }
+          const T ha = T(0.5) * ab;
 #pragma unroll
           for (int v = 0; v < V; ++v)
             fn[b][v] = fma(-ha, uR[v] - uL[v], T(0.5) * (fL[b][v] + fR[b][v]));

@@ -468,7 +468,8 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
       delete m;
       return fail(CRKDG_E_UNSUPPORTED, "problem " + std::to_string(i) +
                                            ": the per-point and global Lax-Friedrichs alpha are not built "
-                                           "for this dim/k/space/system (3D Q^2 Euler)");
+                                           "for this dim/k/space/system/precision (3D Q^2 Euler, 2D P^3 "
+                                           "Euler FP64)");
     }
     int64_t nc = 1;
     for (int d = 0; d < p.dim; ++d) nc *= p.n[d];

@@ -58,7 +58,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Ops {
   static VariantOps make() {
     return VariantOps{D, K, SP, SYS, sizeof(T) == 8 ? CRKDG_FP64 : CRKDG_MIXED,
                       C::M, C::V, C::S::NQ, C::NS, static_cast<int>(sizeof(typename C::Record)), C::WALLS ? 1 : 0,
-                      C::BIG ? 0 : 1,
+                      C::ALPHA_MODES ? 1 : 0,
                       &stage_local, &stage_final, &limit, &cfl, &project, &queue_local, &queue_final,
                       &stage_local_p, &stage_final_p, &stage_inner_dg, &stage_inner_dg_p};
   }

@@ -45,8 +45,8 @@ def _states(mesh, coeffs):
     return out
 
 
-FINAL_CASES = ["euler2d_q1_outflow", "euler2d_q2", "euler2d_q3", "euler2d_p1", "euler2d_p2", "euler2d_p3",
-               "euler3d_q1", "euler3d_p1", "burgers1d_p2", "euler1d_p3_outflow"]
+FINAL_CASES = ["euler2d_q1_outflow", "euler2d_q2", "euler2d_q3", "euler2d_p1", "euler2d_p2", "euler3d_q1",
+               "euler3d_p1", "burgers1d_p2", "euler1d_p3_outflow"]
 
 
 @pytest.mark.parametrize("alpha", ["point", "global"])
@@ -88,7 +88,8 @@ def test_alpha_final_stage_parity(lib, name, alpha):
 
 
 @pytest.mark.parametrize("name,precision,alpha,scheme", [
-    ("euler2d_q2", "fp64", "point", "crkdg"), ("euler2d_p3", "fp64", "point", "crkdg"),
+    ("euler2d_q2", "fp64", "point", "crkdg"), ("euler2d_p3", "mixed", "point", "crkdg"),
+    ("euler2d_p3", "mixed", "global", "crkdg"),
     ("euler3d_q1", "fp64", "point", "crkdg"), ("euler2d_q2", "mixed", "point", "crkdg"),
     ("euler2d_p2", "mixed", "point", "crkdg"), ("euler2d_q2", "fp64", "global", "crkdg"),
     ("euler3d_p1", "fp64", "global", "crkdg"), ("euler2d_q2", "fp64", "global", "rkdg"),
@@ -171,9 +172,41 @@ def test_point_alpha_batch_with_both_forms(lib):
 
 
 @pytest.mark.parametrize("alpha", ["point", "global"])
-def test_alpha_options_not_built_for_3d_q2_euler(lib, alpha):
-    """3D Q^2 Euler keeps only the per-face alpha (its face loop runs at the
-    register limit); asking for another form fails at init."""
+@pytest.mark.parametrize("name,precision", [("euler3d_q2", "fp64"), ("euler3d_q2", "mixed"), ("euler2d_p3", "fp64")])
+def test_alpha_options_not_built(lib, name, precision, alpha):
+    """3D Q^2 Euler (its face loop runs at the register limit) and 2D P^3
+    Euler FP64 (the option code alone makes it spill) keep only the per-face
+    alpha; asking for another form fails at init, the per-face form works."""
     with pytest.raises(lib.CRKDGError) as e:
-        lib.Mesh(gpu_problem(dict(CASES["euler3d_q2"], precision="fp64", alpha=alpha)))
+        lib.Mesh(gpu_problem(dict(CASES[name], precision=precision, alpha=alpha)))
     assert e.value.code == lib.E_UNSUPPORTED
+    lib.Mesh(gpu_problem(dict(CASES[name], precision=precision, alpha="face")))
+
+
+@pytest.mark.parametrize("alpha", ["point", "global"])
+@pytest.mark.parametrize("name", ["euler2d_q2_quadrant", "euler2d_p2_walls", "euler3d_p1_sides"])
+def test_alpha_with_walls_and_dirichlet_sides(lib, name, alpha):
+    """Reflective walls and Dirichlet sides through the alpha options: three
+    controller steps against the oracle (the boundary faces take their
+    alpha from the interior trace and the ghost state like any face)."""
+    from test_gpu_boundaries import CASES as BC_CASES
+    params = dict(BC_CASES[name], precision="fp64", alpha=alpha)
+    o = oracle.CRKDG(oracle_problem(params))
+    mesh = lib.Mesh(gpu_problem(params))
+    C0 = random_state(o, seed=161, rel_amp=0.1)
+    slots = mesh.new_slots()
+    mesh.set_legendre(slots[0], C0)
+    ctl = mesh.new_ctl()
+    mesh.start(slots, ctl, t0=0.0)
+    U = o.from_legendre(C0)
+    t = 0.0
+    for n in range(3):
+        _say(f"[{alpha} alpha boundaries] {name} step {n}")
+        U, info_o = o.step(U, t)
+        t = info_o["t"]
+        info = mesh.step(slots, ctl)[0]
+        assert info["status"] == 0 and info["halvings"] == info_o["halvings"]
+        assert math.isclose(info["dt"], info_o["dt"], rel_tol=1e-12)
+        err = rel_err_per_var(mesh.get_legendre(slots[info["cur"]]), o.to_legendre(U))
+        _say(f"   dt {info['dt']:.4e} rel err {err:.2e}")
+        assert err < 10 * FP64_TOL
