@@ -41,7 +41,10 @@ design notes of the repository):
       Optional (Problem.alpha = "point"): alpha at each face quadrature point
       from its two traces alone (local LF); Prop. 2.1's bound argument holds
       pointwise, since each point's alpha still bounds the wave speed of both
-      of its traces.  Optional (Problem.alpha = "global"): one alpha for every
+      of its traces.  A trace with p < 0 has no real sound speed: the maxima
+      skip it, and a point where both traces lack one takes the face alpha
+      (only inadmissible traces, e.g. FP32 cancellation near vacuum, reach
+      this).  Optional (Problem.alpha = "global"): one alpha for every
       face of every stage of a step, the a0 of Sec. 2.1 taken as the maximum
       over directions of a0_d(u~^n) (A5); stage values whose wave speeds
       exceed it are caught by the average check and halving (A10).
@@ -493,9 +496,15 @@ class CRKDG:
         (Sec. 2.1); um/up [c, b, V] interior/exterior traces.  alpha per face
         (reading A1), per face point (alpha = "point"), or the given a_glob
         (alpha = "global")."""
-        a = np.maximum(self.wave_speed(um, dd), self.wave_speed(up, dd))     # [c, b]
+        with np.errstate(invalid="ignore"):
+            a = np.fmax(self.wave_speed(um, dd), self.wave_speed(up, dd))    # [c, b]
+        a_face = np.max(np.where(np.isnan(a), 0.0, a), axis=1)     # over the defined speeds
         if self.p.alpha == "face":
-            a = np.broadcast_to(a.max(axis=1)[:, None], a.shape)
+            a = np.broadcast_to(a_face[:, None], a.shape)
+        elif self.p.alpha == "point":
+            # a point whose two traces have no real sound speed (p < 0) takes
+            # the face's alpha
+            a = np.where(np.isnan(a), a_face[:, None], a)
         elif self.p.alpha == "global":
             if a_glob is None:
                 raise ValueError("the global alpha needs a_glob")
