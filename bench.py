@@ -63,6 +63,9 @@ def parse():
                          "empty for none)")
     ap.add_argument("--only", choices=["euler3d", "batched", "euler2d_rkdg"], default=None,
                     help="run only this extra workload and print its results (for profiling)")
+    ap.add_argument("--alpha", choices=["face", "point", "global"], default="face",
+                    help="Lax-Friedrichs alpha of the 2D workloads (headline and euler2d_rkdg): per face "
+                         "(default), per face point, or the global a0")
     ap.add_argument("--kernel-reps", type=int, default=20)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (to scale HBM byte counters)")
@@ -95,17 +98,20 @@ def wave3d_state(mesh, state, case, n, torch):
     mesh.project(smp.reshape(-1), state)
 
 
-def setup(name, precision, crkdg, inputs, torch, n2d):
+def setup(name, precision, crkdg, inputs, torch, n2d, alpha="face"):
     scheme = "crkdg"
+    extra = {}
     if name in ("euler2d", "euler2d_rkdg"):
         cases = [inputs.euler_2d_voronoi(seed=0, n=n2d)]
+        extra["alpha"] = alpha
         if name == "euler2d_rkdg":
             scheme = "rkdg"     # same workload, standard RKDG (F in every stage)
     elif name == "euler3d":
         cases = [inputs.euler_3d_wave(seed=0, n=128)]
     else:
         cases = inputs.batched_2d(seed=0)
-    probs = [crkdg.problem_from_params(dict(c.params, precision=precision, scheme=scheme)) for c in cases]
+    probs = [crkdg.problem_from_params(dict(c.params, precision=precision, scheme=scheme, **extra))
+             for c in cases]
     mesh = crkdg.Mesh(probs)
     slots = mesh.new_slots()
     if name == "euler3d":
@@ -178,7 +184,7 @@ def run_graph(graph, torch, stream):
 def measure(name, precision, args, crkdg, inputs, torch, stream, kernels=True, batched=False):
     """Autotune the launch shapes, then time the steps (batched: warm-up and
     timed steps as two captured step graphs, one launch each)."""
-    cases, mesh, slots, ctl = setup(name, precision, crkdg, inputs, torch, args.n)
+    cases, mesh, slots, ctl = setup(name, precision, crkdg, inputs, torch, args.n, args.alpha)
     # launch shapes from the library's autotuner (results do not depend on them)
     tuning = mesh.autotune(slots, ctl, reps=1 if name == "euler3d" else 2)
     if batched:
@@ -382,7 +388,7 @@ def main():
         "data": "synthetic (seeded 64-site Voronoi states)",
         "config": {"workload": f"2D Euler Q2 modal DG, {args.n}x{args.n} periodic, 3-stage cRKDG "
                                f"(Heun3) + scaling limiter, mixed precision",
-                   "cells": Nc, "modes": M, "vars": V, "stages": s, "dof": dof},
+                   "cells": Nc, "modes": M, "vars": V, "stages": s, "dof": dof, "lf_alpha": args.alpha},
         "accepted_steps": mixed["accepted"],
         "rejected_attempts": mixed["rejected"],
         "kernel_ms": {f"stage{i}": v for i, v in mixed["kern"].items()},
@@ -392,7 +398,8 @@ def main():
         # u~^{n+1}); its event time covers the stage kernel and the deferred
         # limiter kernel that completes it (plus a ~2 us queue-counter reset)
         "roofline": {"bound": "hbm", "achieved": fin["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": fin["achieved"] / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "frac": fin["achieved"] / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if args.alpha == "face" else None,
                      "kernel": "k_stage_final<2,2,Q,Euler,float> + k_limit_queue<...,final>",
                      "alg_bytes_per_launch": fin["alg_bytes"], "kernel_ms": fin["kernel_ms"]},
     }

@@ -957,8 +957,11 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
           T ab = alpha;
           if (ALPHA_MODES && I.alpha_mode == CRKDG_ALPHA_POINT) {
             // the point's own speed, recomputed so that the per-face form
-            // keeps no per-point values alive
-            ab = fmax(P::speed(uL, P::aux(uL, I), d, I), P::speed(uR, P::aux(uR, I), d, I));
+            // keeps no per-point values alive (bitwise the value the face
+            // maximum saw, so the fmin is exact); where both traces have an
+            // undefined sound speed (a non-positive pressure from FP32
+            // cancellation near vacuum) fmin falls back to the face alpha
+            ab = fmin(fmax(P::speed(uL, P::aux(uL, I), d, I), P::speed(uR, P::aux(uR, I), d, I)), alpha);
           }
           const T ha = T(0.5) * ab;
 #pragma unroll
