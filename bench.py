@@ -240,16 +240,42 @@ def l1_diff(mesh_a, slots_a, cur_a, mesh_b, slots_b, cur_b, torch):
     return worst
 
 
-def measured_traffic():
-    """HBM bytes per launch of the final-stage kernel from the committed
-    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None when the kernel
-    sources changed since the counters were taken."""
+def _committed_counters():
+    """The committed rocprofv3 counter summary of the final-stage kernel, or
+    None when the kernel sources changed since the counters were taken."""
     from pathlib import Path
     f = Path(ROOT) / "profiles" / "traffic_final_stage_euler2d_q2_1024_mixed.json"
     if not f.exists():
         return None
     d = json.loads(f.read_text())
-    return d["traffic_bytes_per_launch"] if d.get("source_hash") == kernel_source_hash() else None
+    return d if d.get("source_hash") == kernel_source_hash() else None
+
+
+def measured_traffic():
+    """HBM bytes per launch of the final-stage kernel (FETCH_SIZE +
+    WRITE_SIZE, scaled by a plain copy), or None."""
+    d = _committed_counters()
+    return d["traffic_bytes_per_launch"] if d else None
+
+
+# VALU issue: a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles
+# (full-rate FP32 and FP64 ops; transcendentals take longer), 4 SIMDs per CU
+VALU_CYCLES_PER_INSTR = 4
+SIMDS = 256 * 4
+CLOCK_HZ = 2.4e9
+
+
+def valu_issue(kernel_ms):
+    """The final stage's VALU instruction-issue floor from the committed
+    SQ_INSTS_VALU / SQ_WAVES counts, and the fraction of the measured time it
+    accounts for (None without counters for these sources)."""
+    d = _committed_counters()
+    if not d or "valu_instr_per_wave" not in d:
+        return None
+    instr, waves = d["valu_instr_per_wave"], d["waves_per_launch"]
+    floor_ms = instr * VALU_CYCLES_PER_INSTR * waves / SIMDS / CLOCK_HZ * 1e3
+    return {"instr_per_wave": instr, "waves_per_launch": waves, "issue_floor_ms": floor_ms,
+            "frac": floor_ms / kernel_ms}
 
 
 # the sources the headline final-stage kernel and its launch are built from
@@ -402,6 +428,9 @@ def main():
                      "traffic": measured_traffic() if args.alpha == "face" else None,
                      "kernel": "k_stage_final<2,2,Q,Euler,float> + k_limit_queue<...,final>",
                      "alg_bytes_per_launch": fin["alg_bytes"], "kernel_ms": fin["kernel_ms"]},
+        # the same launch against its VALU instruction-issue floor (the
+        # kernel is VALU-bound: the floor exceeds the HBM time of its bytes)
+        "valu": valu_issue(fin["kernel_ms"]) if args.alpha == "face" else None,
     }
     if "fp64" in results:
         f = results["fp64"]
