@@ -85,9 +85,11 @@ extern "C" {
 
 #define CRKDG_ALPHA_FACE 0  /* Lax-Friedrichs alpha per face: largest wave speed over the face's
                                quadrature points and both traces (the reading of Sec. 2.1 used
-                               throughout) */
+                               throughout); a trace without a real sound speed (pressure < 0,
+                               e.g. FP32 rounding near vacuum) is skipped */
 #define CRKDG_ALPHA_POINT 1 /* alpha at each face quadrature point from its two traces (local
-                               Lax-Friedrichs / Rusanov) */
+                               Lax-Friedrichs / Rusanov); a point where neither trace has a real
+                               sound speed takes the face alpha */
 #define CRKDG_ALPHA_GLOBAL 2 /* one alpha for every face: the wave-speed maximum a0 of Sec. 2.1,
                                max over d of crkdg_ctl.a0[d] (that of u~^n over S_K, which the
                                controller holds during a step; a caller of crkdg_stage sets it).

@@ -1047,6 +1047,10 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
   template <bool A0>
   __device__ __forceinline__ static bool sk_pass(const State& s, const InstDev& I, double* a0) {
     T ub[V], err[V], bnd[V];
+    // wave speeds are maximised in T and widened once (exact and monotone)
+    T am[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) am[d] = T(0);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       ub[v] = T(s.ub[v]);
@@ -1088,7 +1092,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
         if constexpr (A0) {
           const auto ax = P::aux(u, I);
 #pragma unroll
-          for (int d = 0; d < D; ++d) a0[d] = fmax(a0[d], static_cast<double>(P::speed(u, ax, d, I)));
+          for (int d = 0; d < D; ++d) am[d] = fmax(am[d], P::speed(u, ax, d, I));
         }
       };
       if constexpr (SF) {
@@ -1120,7 +1124,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
         if constexpr (A0) {
           const auto ax = P::aux(&a, I);
 #pragma unroll
-          for (int d = 0; d < D; ++d) a0[d] = fmax(a0[d], static_cast<double>(P::speed(&a, ax, d, I)));
+          for (int d = 0; d < D; ++d) am[d] = fmax(am[d], P::speed(&a, ax, d, I));
         }
       };
       if constexpr (SF) {
@@ -1137,6 +1141,10 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
           check(&a);
         }
       }
+    }
+    if constexpr (A0) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) a0[d] = fmax(a0[d], static_cast<double>(am[d]));
     }
     return ok;
   }
