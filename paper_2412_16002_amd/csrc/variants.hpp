@@ -75,5 +75,6 @@ int variants_v3d_q1(const VariantOps** out);
 int variants_v3d_q2_adv(const VariantOps** out);
 int variants_v3d_q2_euler(const VariantOps** out);
 int variants_v3d_p(const VariantOps** out);
+int variants_v3d_p2_euler(const VariantOps** out);
 
 }  // namespace crkdg

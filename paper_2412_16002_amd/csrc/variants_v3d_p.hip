@@ -1,6 +1,6 @@
 // Compiled variants: 3D P^1 (total degree) advection / Euler and P^2
-// advection; FP64 and mixed precision.  (3D P^2 Euler, fully unrolled,
-// spills to scratch and compiles for minutes: not built.)
+// advection; FP64 and mixed precision.  (3D P^2 Euler: mixed form only, in
+// its own translation unit, variants_v3d_p2_euler.hip.)
 #include "variants.hpp"
 
 namespace crkdg {
