@@ -32,8 +32,8 @@ def lib():
     return crkdg
 
 
-def _error(lib, dim, n, k, precision, t_end, amp=0.5):
-    case = inputs.euler_wave(dim, (n,) * dim, k, amp=amp, precision=precision)
+def _error(lib, dim, n, k, precision, t_end, amp=0.5, space="Q"):
+    case = inputs.euler_wave(dim, (n,) * dim, k, space=space, amp=amp, precision=precision)
     params = dict(case.params, precision=precision)
     o = oracle.CRKDG(oracle_problem(params))        # evaluates DG functions only
     mesh = lib.Mesh(gpu_problem(params))
