@@ -86,17 +86,19 @@ def test_density_wave_converges_at_order_k_plus_1(lib, dim, k, meshes, t_end):
         assert math.log2(em[-2] / em[-1]) > k + 1 - slack
 
 
-@pytest.mark.parametrize("k", [1, 2])
-def test_near_vacuum_density_wave_converges(lib, k):
+@pytest.mark.parametrize("k,space,meshes", [(1, "Q", (16, 32, 64)), (2, "Q", (16, 32, 64)),
+                                            (1, "P", (16, 32, 64)), (2, "P", (16, 32, 64)),
+                                            (3, "P", (8, 16, 32))])
+def test_near_vacuum_density_wave_converges(lib, k, space, meshes):
     """The same wave with amplitude 0.99 (density down to 0.01, the
     near-zero-density character of the second accuracy scenario of the 2D
-    Euler example), 2D Q^k on 16^2 .. 64^2 to t = 0.02: order k+1 in FP64,
-    the mixed form at the same error."""
+    Euler example, whose table lists both P^k and Q^k), 2D Q^k and P^k to
+    t = 0.02: order k+1 in FP64, the mixed form at the same error."""
     errs = {}
     for precision in ("fp64", "mixed"):
-        errs[precision] = [_error(lib, 2, n, k, precision, 0.02, amp=0.99)[0] for n in (16, 32, 64)]
+        errs[precision] = [_error(lib, 2, n, k, precision, 0.02, amp=0.99, space=space)[0] for n in meshes]
         rates = [math.log2(a / b) for a, b in zip(errs[precision], errs[precision][1:])]
-        _say(f"[wave 2D Q{k} amp 0.99 {precision}] errors {['%.3e' % e for e in errs[precision]]} "
+        _say(f"[wave 2D {space}{k} amp 0.99 {precision}] errors {['%.3e' % e for e in errs[precision]]} "
              f"rates {['%.2f' % r for r in rates]}")
     ef, em = errs["fp64"], errs["mixed"]
     assert math.log2(ef[-2] / ef[-1]) > k + 1 - 0.3
