@@ -15,8 +15,9 @@
  * Sec. 3.3, the scaling limiters of Sec. 2.2.2 (scalar, Prop. 2.4) and
  * Sec. 2.2.3 (Euler, density then internal energy), and the adaptive halving
  * strategy of Sec. 4.1.  Options of each problem: the standard RKDG scheme
- * of Sec. 2.1 instead (F in every stage, scheme = CRKDG_SCHEME_RKDG), and
- * periodic, outflow, reflective or Dirichlet / inflow sides.
+ * of Sec. 2.1 instead (F in every stage, scheme = CRKDG_SCHEME_RKDG),
+ * periodic, outflow, reflective or Dirichlet / inflow sides, and the
+ * Lax--Friedrichs alpha per face, per face point or global (CRKDG_ALPHA_*).
  *
  * Conventions shared by every entry point
  * ----------------------------------------
@@ -223,7 +224,10 @@ const char *crkdg_last_error(void);
  * Prop. 2.1; S_K = Gauss x Gauss--Lobatto points, Prop. 2.2 and Fig. 1),
  * upload them, and fill *layout.  Synchronous.  Errors: CRKDG_E_ARG for an
  * invalid problem, CRKDG_E_UNSUPPORTED for a combination not compiled,
- * CRKDG_E_HIP. */
+ * CRKDG_E_HIP.  Compiled, each in FP64 and mixed form: 1D P^1-P^3 (all
+ * systems); 2D Q^1-Q^3 and P^1-P^3 (advection, Euler); 3D Q^1 and P^1
+ * (advection, Euler), Q^2 and P^2 advection, Q^2 Euler; 3D P^2 Euler in the
+ * mixed form only.  Burgers is 1D only. */
 int crkdg_init_mesh(const crkdg_problem *problems, int32_t n_inst, crkdg_mesh **out,
                     crkdg_layout *layout);
 
