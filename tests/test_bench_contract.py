@@ -27,3 +27,19 @@ def test_traffic_counters_are_used_only_for_the_sources_they_describe():
     d = json.loads(f.read_text())
     expected = d["traffic_bytes_per_launch"] if d["source_hash"] == bench.kernel_source_hash() else None
     assert bench.measured_traffic() == expected
+
+
+def test_valu_issue_floor_follows_the_counters(monkeypatch):
+    """The VALU issue floor is SQ_INSTS_VALU per wave x 4 cycles x waves over
+    1024 SIMDs at 2.4 GHz, reported only for the sources the counters
+    describe."""
+    sys.path.insert(0, str(ROOT))
+    import bench
+    d = {"source_hash": "x", "traffic_bytes_per_launch": 1.0, "valu_instr_per_wave": 1000.0,
+         "waves_per_launch": 2048.0}
+    monkeypatch.setattr(bench, "_committed_counters", lambda: d)
+    v = bench.valu_issue(0.01)
+    floor_ms = 1000.0 * 4 * 2048.0 / 1024 / 2.4e9 * 1e3
+    assert abs(v["issue_floor_ms"] - floor_ms) < 1e-15 and abs(v["frac"] - floor_ms / 0.01) < 1e-12
+    monkeypatch.setattr(bench, "_committed_counters", lambda: None)
+    assert bench.valu_issue(0.01) is None and bench.measured_traffic() is None
