@@ -87,10 +87,10 @@ extern "C" {
 #define CRKDG_ALPHA_FACE 0  /* Lax-Friedrichs alpha per face: largest wave speed over the face's
                                quadrature points and both traces (the reading of Sec. 2.1 used
                                throughout); a trace without a real sound speed (pressure < 0,
-                               e.g. FP32 rounding near vacuum) is skipped */
+                               e.g. FP32 rounding near vacuum) counts with its flow speed |w_d| */
 #define CRKDG_ALPHA_POINT 1 /* alpha at each face quadrature point from its two traces (local
-                               Lax-Friedrichs / Rusanov); a point where neither trace has a real
-                               sound speed takes the face alpha */
+                               Lax-Friedrichs / Rusanov); a point whose speeds are undefined (a
+                               zero or non-finite density) takes the face alpha */
 #define CRKDG_ALPHA_GLOBAL 2 /* one alpha for every face: the wave-speed maximum a0 of Sec. 2.1,
                                max over d of crkdg_ctl.a0[d] (that of u~^n over S_K, which the
                                controller holds during a step; a caller of crkdg_stage sets it).
@@ -258,9 +258,14 @@ int crkdg_project(crkdg_mesh *mesh, const double *d_samples, crkdg_state out, vo
  * d_ctl may be NULL (no flags).  Asynchronous. */
 int crkdg_limit(crkdg_mesh *mesh, crkdg_state u, crkdg_ctl *d_ctl, void *stream);
 
-/* Cell averages in natural cell order, d_avg[v][K] per instance (same packing
- * as a state's avg array; may be NULL), and d_totals[inst][v] = sum_K |K|
- * ubar_K by a fixed-order tree reduction (may be NULL). Asynchronous. */
+/* Cell averages (mode 0 of the Legendre basis is the average of u over K,
+ * Sec. 2.1) in natural cell order, d_avg[v][K] per instance (same packing as
+ * a state's avg array; may be NULL), and d_totals[inst][v] = sum_K |K| ubar_K
+ * by a fixed-order tree reduction (may be NULL): the conserved totals, which
+ * a periodic cRKDG step keeps unchanged (the local conservation remark at the
+ * end of Sec. 3.2).  Deterministic: the same state gives bitwise the same
+ * totals.  Uses a mesh-owned partial-sum buffer, so two calls on one mesh
+ * must not overlap on different streams.  Asynchronous. */
 int crkdg_cell_avg(crkdg_mesh *mesh, crkdg_state u, double *d_avg, double *d_totals,
                    void *stream);
 

@@ -41,10 +41,10 @@ design notes of the repository):
       Optional (Problem.alpha = "point"): alpha at each face quadrature point
       from its two traces alone (local LF); Prop. 2.1's bound argument holds
       pointwise, since each point's alpha still bounds the wave speed of both
-      of its traces.  A trace with p < 0 has no real sound speed: the maxima
-      skip it, and a point where both traces lack one takes the face alpha
-      (only inadmissible traces, e.g. FP32 cancellation near vacuum, reach
-      this).  Optional (Problem.alpha = "global"): one alpha for every
+      of its traces.  A trace with p < 0 has no real sound speed: its speed
+      is the flow speed |w_d| (c^2 clamped at zero; only inadmissible traces,
+      e.g. FP32 cancellation near vacuum, reach this), and a point whose
+      speeds are undefined (zero density) takes the face alpha.  Optional (Problem.alpha = "global"): one alpha for every
       face of every stage of a step, the a0 of Sec. 2.1 taken as the maximum
       over directions of a0_d(u~^n) (A5); stage values whose wave speeds
       exceed it are caught by the average check and halving (A10).
@@ -442,7 +442,11 @@ class CRKDG:
         mom = u[..., 1:1 + self.d]
         E = u[..., 1 + self.d]
         pres = (p.gamma - 1.0) * (E - 0.5 * np.sum(mom * mom, axis=-1) / rho)
-        return np.abs(mom[..., dd] / rho) + np.sqrt(p.gamma * pres / rho)
+        # a state with p < 0 (not admissible: FP32 cancellation near vacuum)
+        # has no real sound speed; its speed is |w_dd| (c^2 clamped at zero),
+        # so the flow speed still bounds the alpha of its face
+        c2 = np.fmax(p.gamma * pres / rho, 0.0)
+        return np.abs(mom[..., dd] / rho) + np.sqrt(c2)
 
     # ---------------- mesh connectivity ----------------
     def neighbour(self, cells, dd, side):
@@ -502,8 +506,8 @@ class CRKDG:
         if self.p.alpha == "face":
             a = np.broadcast_to(a_face[:, None], a.shape)
         elif self.p.alpha == "point":
-            # a point whose two traces have no real sound speed (p < 0) takes
-            # the face's alpha
+            # a point whose two speeds are undefined (zero density) takes the
+            # face's alpha
             a = np.where(np.isnan(a), a_face[:, None], a)
         elif self.p.alpha == "global":
             if a_glob is None:
@@ -696,25 +700,43 @@ class CRKDG:
         """u at the S_K points: [c, P, V]."""
         return np.einsum("cvm,pm->cpv", U, self.phi_s)
 
-    def bound_violations(self, U, rel=1e-12):
-        """Number of cells with an S_K value outside B (B^eps for Euler) or
-        non-finite.  Round-off slack: `rel` times the magnitude of the cell's
-        average of the checked quantity (the evaluation at the points carries
-        an absolute error of that size)."""
-        us = self.sk_values(U)
-        avg = self.cell_average(U)
+    def bound_violations(self, U):
+        """Number of cells with an S_K value outside B (B^eps for Euler), a
+        non-positive density, or a non-finite value.
+
+        The values are taken from the Legendre coefficients C of U (every
+        Legendre product satisfies |L_m| <= 1 on the cell).  A point counts
+        as outside only beyond the FP64 rounding of its value: the coefficient
+        conversion and the evaluation are sums of at most M + Q products, so
+        tol_v = 8 (M + Q) 2^-53 sum_m |C_v,m|; for Euler the check is
+        q = E rho - |m|^2 / 2 >= eps rho (rho e >= eps times rho > 0) with
+        those errors carried through the products.  Scalar bounds also allow
+        the round-off margin of the average check (A24).  Internal energy
+        must be strictly positive wherever FP64 resolves eps rho (its
+        tolerance is below eps rho)."""
+        C = self.to_legendre(U)
+        L = self._legendre_at(self.xs)                                 # [P, M]
+        us = np.einsum("cvm,pm->cpv", C, L)
+        u53 = 2.0 ** -53
+        tol = 8.0 * (self.M + len(self.wq)) * u53 * np.sum(np.abs(C), axis=2)     # [c, V]
         p = self.p
         bad = ~np.all(np.isfinite(us), axis=(1, 2))
         with np.errstate(invalid="ignore", divide="ignore"):
             if p.system == EULER:
-                tol_r = rel * np.abs(avg[:, 0])
-                tol_e = rel * (np.abs(avg[:, -1]) + np.abs(self.rho_e(avg)))
-                bad |= np.any(us[..., 0] < p.eps - tol_r[:, None], axis=1)
-                bad |= np.any(self.rho_e(us) < p.eps - tol_e[:, None], axis=1)
+                d = self.d
+                rho, mom, E = us[..., 0], us[..., 1:1 + d], us[..., 1 + d]
+                tr, tm, tE = tol[:, None, 0], tol[:, None, 1:1 + d], tol[:, None, 1 + d]
+                q = E * rho - 0.5 * np.sum(mom * mom, axis=-1)
+                tol_q = (tE * np.abs(rho) + tr * np.abs(E) + np.sum(tm * np.abs(mom), axis=-1)
+                         + 4.0 * u53 * (np.abs(E * rho) + 0.5 * np.sum(mom * mom, axis=-1)))
+                bad |= np.any(rho <= 0.0, axis=1)
+                bad |= np.any(rho < p.eps - tr, axis=1)
+                bad |= np.any(q < p.eps * rho - tol_q, axis=1)
+                bad |= np.any((q <= 0.0) & (tol_q < p.eps * rho), axis=1)
             else:
-                tol = rel * np.maximum(np.abs(avg[:, 0]), 1.0)
-                bad |= np.any(us[..., 0] > p.bound_hi + tol[:, None], axis=1)
-                bad |= np.any(us[..., 0] < p.bound_lo - tol[:, None], axis=1)
+                t = tol[:, None, 0] + self.average_slack()
+                bad |= np.any(us[..., 0] > p.bound_hi + t, axis=1)
+                bad |= np.any(us[..., 0] < p.bound_lo - t, axis=1)
         return int(np.sum(bad))
 
     def l1_norm(self, U, ref_fn=None, npts=None):

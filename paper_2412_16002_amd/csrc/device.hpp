@@ -232,7 +232,9 @@ template <int D, int SYS> struct Phys {
     }
   }
 
-  // largest |eigenvalue| of df_d/du
+  // largest |eigenvalue| of df_d/du; a state with p < 0 (not admissible:
+  // FP32 cancellation near vacuum) has no real sound speed, and its speed is
+  // the flow speed |w_d| (c^2 clamped at zero), which still bounds alpha
   template <typename T>
   __device__ __forceinline__ static T speed(const T* u, const Aux<T>& a, int d, const InstDev& I) {
 #pragma clang fp contract(off)
@@ -241,7 +243,7 @@ template <int D, int SYS> struct Phys {
     } else if constexpr (SYS == SYS_BURG) {
       return fabs(u[0]);
     } else {
-      return fabs(a.w[d]) + fsqrt(T(I.gamma) * a.p * a.ir);
+      return fabs(a.w[d]) + fsqrt(fmax(T(I.gamma) * a.p * a.ir, T(0)));
     }
   }
 };
@@ -958,9 +960,8 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
           if (ALPHA_MODES && I.alpha_mode == CRKDG_ALPHA_POINT) {
             // the point's own speed, recomputed so that the per-face form
             // keeps no per-point values alive (bitwise the value the face
-            // maximum saw, so the fmin is exact); where both traces have an
-            // undefined sound speed (a non-positive pressure from FP32
-            // cancellation near vacuum) fmin falls back to the face alpha
+            // maximum saw, so the fmin is exact); a NaN speed (a zero or
+            // non-finite density) falls back to the face alpha
             ab = fmin(fmax(P::speed(uL, P::aux(uL, I), d, I), P::speed(uR, P::aux(uR, I), d, I)), alpha);
           }
           const T ha = T(0.5) * ab;

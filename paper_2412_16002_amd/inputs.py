@@ -169,7 +169,7 @@ def euler_3d_blast(seed=0, n=128, precision="mixed"):
 
 
 def sedov_2d(n=160, k=2, space="Q", precision="fp64", length=1.1, eps=1e-13):
-    """The Sedov blast of the 2D examples (Sec. 4.3): [0, 1.1]^2, rho = 1,
+    """The Sedov blast of the 2D examples (Sec. 4.4, Example 4.7): [0, 1.1]^2, rho = 1,
     w = 0, E = 1e-12 except E = 0.244816 / dx^2 in the corner cell; reflective
     walls on the lower sides, outflow on the upper ones (the blast's energy
     makes the shock reach radius 1 at t = 1).  eps below the background

@@ -1,4 +1,4 @@
-"""The 1D Euler Riemann examples of Sec. 4.2 with Dirichlet ends on the GPU:
+"""The 1D examples of Sec. 4.3 with Dirichlet ends (Examples 4.3-4.5) on the GPU:
 the Lax shock tube ([-5, 5], t = 1.3) and the double rarefaction ([-1, 1],
 t = 0.6), 200 cells, P^2 and P^3, FP64 and mixed.  Lockstep with the FP64
 oracle over the first steps, then the full run against the exact Riemann
@@ -89,7 +89,7 @@ def test_paper_1d_example(lib, name, k, precision):
 
 @pytest.mark.parametrize("k,precision", [(2, "fp64"), (3, "fp64"), (2, "mixed"), (3, "mixed")])
 def test_heaviside_inflow_example(lib, k, precision):
-    """Sec. 4.2 traveling Heaviside example (u0 = 1, inflow 2 = the upper
+    """Sec. 4.3 traveling Heaviside example (Example 4.3; u0 = 1, inflow 2 = the upper
     bound, 200 cells) to t = 0.5: the same accepted steps as the oracle
     (the average check's round-off margin keeps the cell at the inflow from
     being rejected), no violations, the inflow mass identity, the front at

@@ -1,4 +1,4 @@
-"""The Sedov blast of the 2D examples (Sec. 4.3) on the GPU: a quadrant
+"""The Sedov blast of the 2D examples (Sec. 4.4, Example 4.7) on the GPU: a quadrant
 [0, 1.1]^2 with reflective walls on the lower sides and outflow on the upper
 ones, all the blast energy in the corner cell, background pressure 4e-13.
 

@@ -219,11 +219,13 @@ def test_global_alpha_conserves_and_converges():
     assert math.log2(errs[0] / errs[1]) > k + 1 - 0.3, errs
 
 
-def test_point_alpha_falls_back_to_the_face_alpha_without_a_sound_speed():
+def test_point_alpha_without_a_sound_speed_takes_the_flow_speed():
     """A face point whose two traces both have p < 0 (no real sound speed)
-    takes the face's alpha: the largest defined speed on that face; the
-    other points keep their own."""
+    takes the larger flow speed |w_d| of its traces (c^2 clamped at zero),
+    not a NaN and not zero; the other points keep their own speeds, and the
+    per-face alpha is the largest of all of them."""
     o = CRKDG(Problem(dim=2, n=(4, 4), system=EULER, k=2, stages=3, alpha="point"))
+    of = CRKDG(Problem(dim=2, n=(4, 4), system=EULER, k=2, stages=3, alpha="face"))
     rng = np.random.default_rng(5)
     rho = rng.uniform(0.5, 1.5, (1, 3))
     w = rng.uniform(-1, 1, (1, 3, 2))
@@ -231,13 +233,16 @@ def test_point_alpha_falls_back_to_the_face_alpha_without_a_sound_speed():
     p[0, 1] = -0.1                                   # middle point: p < 0 on both sides
     um = inputs.conservative(rho, w, p)
     up = inputs.conservative(rho * 1.1, w * 0.9, np.where(p < 0, p, p * 1.2))
-    fl = o.lf_flux(um, up, 0, 1)
-    with np.errstate(invalid="ignore"):
-        ws = np.fmax(o.wave_speed(um, 0), o.wave_speed(up, 0))
-    a_face = np.nanmax(ws)
     central = 0.5 * (o.flux(um, 0) + o.flux(up, 0))
+    fl = o.lf_flux(um, up, 0, 1)
     alpha = (central - fl) / (0.5 * (up - um))       # recovered per point and variable
-    assert np.allclose(alpha[0, 1], a_face, rtol=1e-12)
-    for b in (0, 2):
-        assert np.allclose(alpha[0, b], ws[0, b], rtol=1e-12)
+    c_m = np.sqrt(1.4 * p / rho)
+    c_p = np.sqrt(1.4 * p * 1.2 / (rho * 1.1))
+    want = np.maximum(np.abs(w[0, :, 0]) + np.where(p[0] > 0, c_m[0], 0.0),
+                      np.abs(0.9 * w[0, :, 0]) + np.where(p[0] > 0, c_p[0], 0.0))
+    assert math.isclose(want[1], abs(w[0, 1, 0]), rel_tol=1e-15)        # the flow speed only
+    for b in range(3):
+        assert np.allclose(alpha[0, b], want[b], rtol=1e-12)
     assert np.all(np.isfinite(fl))
+    alpha_f = (central - of.lf_flux(um, up, 0, 1)) / (0.5 * (up - um))
+    assert np.allclose(alpha_f, np.max(want), rtol=1e-12)

@@ -106,7 +106,7 @@ def test_dirichlet_sides_with_the_adjacent_state_equal_outflow(dim):
 @pytest.mark.parametrize("k,stages", [(1, 2), (2, 3), (3, 4)])
 def test_inflow_adds_mass_at_the_closed_form_rate(k, stages):
     """Linear advection (a = 1), u0 = 1, Dirichlet inflow u = 2 on the left,
-    outflow on the right (the inflow example of Sec. 4.2): while the front is
+    outflow on the right (the inflow example of Sec. 4.3, Example 4.3): while the front is
     away from the right end, every step adds dt a (2 - 1) to the total, and
     the solution stays in [1, 2]."""
     p = Problem(dim=1, n=(30,), system=ADVECTION, k=k, stages=stages, vel=(1.0, 0, 0), bc=(DIRICHLET,),
@@ -141,7 +141,7 @@ def _flux1(w, g=1.4):
     return np.array([r * u, r * u * u + p, (p / (g - 1.0) + 0.5 * r * u * u + p) * u])
 
 
-# the 1D Riemann examples of Sec. 4.2 with Dirichlet ends: Lax shock tube
+# the 1D Riemann examples of Sec. 4.3 (Examples 4.4, 4.5) with Dirichlet ends: Lax shock tube
 # on [-5, 5] to t = 1.3, double rarefaction on [-1, 1] to t = 0.6 (its data
 # sit exactly on the vacuum threshold: 2 (c_L + c_R) / (gamma - 1) = u_R - u_L)
 PAPER_1D = {
@@ -200,7 +200,7 @@ def test_paper_1d_riemann_examples_against_exact_solution(name):
 
 
 def heaviside_problem(k, n=200):
-    """Sec. 4.2 traveling Heaviside example: u0 = 1 on [0, 1], inflow u = 2
+    """Sec. 4.3 traveling Heaviside example (Example 4.3): u0 = 1 on [0, 1], inflow u = 2
     on the left (the upper bound of B = [1, 2]), outflow on the right."""
     return Problem(dim=1, n=(n,), system=ADVECTION, k=k, stages=k + 1, vel=(1.0, 0, 0), bc=(DIRICHLET,),
                    bc_upper=(OUTFLOW,), bc_state={0: [2.0]}, bound_lo=1.0, bound_hi=2.0,
