@@ -1,27 +1,30 @@
 """Benchmark of the cRKDG hot path on one MI355X.
 
-Headline workload: 2D compressible Euler on a periodic 1024 x 1024 mesh,
-tensor Q^2 modal DG (9 modes x 4 variables), 3-stage cRKDG (Heun's
-third-order method) with the limiter after every stage, seeded 64-site
-Voronoi states (rho in [1e-3, 1], p in [1e-6, 10], |w| <= 3).  One step = all
-stages (local stages with G, final stage with F and Lax--Friedrichs fluxes,
-the scaling limiter after each, the fused CFL wave-speed maximum) plus the
-device step controller, for the whole mesh.
+Headline workload (the largest single-GPU configuration): 3D compressible
+Euler on a periodic 128^3 mesh, tensor Q^2 modal DG (27 modes x 5
+variables), four-stage cRKDG (classical RK4) with the scaling limiter after
+every stage, seeded smooth translating density wave (rho = 1 + 0.99 sin,
+w = (1, 1, 1), p = 1).  One step = all stages (inner stages with G, the
+final stage with F and Lax--Friedrichs fluxes, the scaling limiter after
+each, the fused CFL wave-speed maximum) plus the device step controller,
+for the whole mesh.
 
 The headline `value` is the mixed-precision form (FP32 modes >= 1, FP64
 averages / checks / limiter theta / average update); the plain FP64 form is
-timed on the same workload and reported beside it with the relative L1
-difference of the two after the same number of steps.
+timed on the same workload and reported beside it, with the relative L1
+difference of their averages after the same steps taken with the same dt
+sequence (the FP64 run's steps replayed in the mixed form).
 
 More workloads are measured in the same run and reported under
 "workloads" (a failure there is reported, never fatal to the headline):
-  euler3d       3D Euler, 128^3 periodic, Q^2 (27 modes x 5 variables), RK4
-                cRKDG, smooth translating density wave (rho = 1 + 0.99 sin);
+  euler2d       2D Euler, 1024^2 periodic, Q^2 (9 modes x 4 variables),
+                Heun3 cRKDG, seeded 64-site Voronoi states
+                (rho in [1e-3, 1], p in [1e-6, 10], |w| <= 3);
   batched       64 independent 2D Euler instances in one mesh,
                 N_i ~ U{64..512}, P^1-P^3, 3 or 4 stages, 16-site Voronoi
                 states, per-instance dt;
-  euler2d_rkdg  the headline workload under the standard RKDG scheme (F in
-                every stage, same Butcher table and limiter), with the
+  euler2d_rkdg  the 2D workload under the standard RKDG scheme (F in every
+                stage, same Butcher table and limiter), with the
                 cRKDG-over-RKDG step-time ratio.
 
 Metric: DOF-stage updates/s = sum over instances of Nc M V x executed stages
@@ -55,18 +58,20 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=1024, help="cells per direction of the headline workload")
+    ap.add_argument("--n", type=int, default=1024, help="cells per direction of the 2D workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
-    ap.add_argument("--workloads", default="euler3d,batched,euler2d_rkdg",
-                    help="extra workloads to measure (comma list of euler3d, batched, euler2d_rkdg; "
+    ap.add_argument("--workloads", default="euler2d,batched,euler2d_rkdg",
+                    help="extra workloads to measure (comma list of euler2d, batched, euler2d_rkdg; "
                          "empty for none)")
-    ap.add_argument("--only", choices=["euler3d", "batched", "euler2d_rkdg"], default=None,
-                    help="run only this extra workload and print its results (for profiling)")
+    ap.add_argument("--only", choices=["euler3d", "euler2d", "batched", "euler2d_rkdg"], default=None,
+                    help="run only this workload (mixed and FP64) and print its results (for profiling)")
     ap.add_argument("--alpha", choices=["face", "point", "global"], default="face",
-                    help="Lax-Friedrichs alpha of the 2D workloads (headline and euler2d_rkdg): per face "
-                         "(default), per face point, or the global a0")
+                    help="Lax-Friedrichs alpha of every workload: per face (default), per face point, "
+                         "or the global a0")
     ap.add_argument("--kernel-reps", type=int, default=20)
+    ap.add_argument("--cpu-budget", type=float, default=10.0,
+                    help="seconds of oracle work per CPU-baseline leg (all threads, then one thread)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (to scale HBM byte counters)")
     return ap.parse_args()
@@ -100,10 +105,9 @@ def wave3d_state(mesh, state, case, n, torch):
 
 def setup(name, precision, crkdg, inputs, torch, n2d, alpha="face"):
     scheme = "crkdg"
-    extra = {}
+    extra = {"alpha": alpha}
     if name in ("euler2d", "euler2d_rkdg"):
         cases = [inputs.euler_2d_voronoi(seed=0, n=n2d)]
-        extra["alpha"] = alpha
         if name == "euler2d_rkdg":
             scheme = "rkdg"     # same workload, standard RKDG (F in every stage)
     elif name == "euler3d":
@@ -240,22 +244,50 @@ def l1_diff(mesh_a, slots_a, cur_a, mesh_b, slots_b, cur_b, torch):
     return worst
 
 
-def _committed_counters():
-    """The committed rocprofv3 counter summary of the final-stage kernel, or
-    None when the kernel sources changed since the counters were taken."""
+# ---------------------------------------------------------------------------
+# committed rocprofv3 counter summaries (they describe a kernel only as long as
+# its sources are unchanged: each summary carries the hash of those sources)
+# ---------------------------------------------------------------------------
+# the sources the headline final-stage kernel and its launch are built from
+# (the 3D Q^2 Euler instantiation, the cooperative and shared device code,
+# tables, launchers, the host code that maps tiles to workgroups, the header)
+HEADLINE_SOURCES = ("include/crkdg.h", "paper_2412_16002_amd/csrc/device.hpp",
+                    "paper_2412_16002_amd/csrc/coop.hpp",
+                    "paper_2412_16002_amd/csrc/tables.hpp", "paper_2412_16002_amd/csrc/variants.hpp",
+                    "paper_2412_16002_amd/csrc/variants_v3d_q2_euler.hip",
+                    "paper_2412_16002_amd/csrc/host.hip")
+HEADLINE_COUNTERS = "profiles/counters_final_stage_euler3d_q2_128_mixed.json"
+
+
+def kernel_source_hash(sources=HEADLINE_SOURCES):
+    """Hash of the sources of a kernel, to tell whether committed counter data
+    still describe the kernel that runs."""
+    import hashlib
     from pathlib import Path
-    f = Path(ROOT) / "profiles" / "traffic_final_stage_euler2d_q2_1024_mixed.json"
+    h = hashlib.sha256()
+    for name in sources:
+        h.update(name.encode())
+        h.update((Path(ROOT) / name).read_bytes())
+    return h.hexdigest()[:16]
+
+
+def _committed_counters(path=HEADLINE_COUNTERS, sources=HEADLINE_SOURCES):
+    """The committed counter summary of a kernel, or None when its sources
+    changed since the counters were taken."""
+    from pathlib import Path
+    f = Path(ROOT) / path
     if not f.exists():
         return None
     d = json.loads(f.read_text())
-    return d if d.get("source_hash") == kernel_source_hash() else None
+    return d if d.get("source_hash") == kernel_source_hash(sources) else None
 
 
 def measured_traffic():
-    """HBM bytes per launch of the final-stage kernel (FETCH_SIZE +
-    WRITE_SIZE, scaled by a plain copy), or None."""
+    """HBM bytes per launch of the headline final-stage kernel (FETCH_SIZE +
+    WRITE_SIZE, scaled by what the same counters read for a plain copy), or
+    None."""
     d = _committed_counters()
-    return d["traffic_bytes_per_launch"] if d else None
+    return d.get("traffic_bytes_per_launch") if d else None
 
 
 # VALU issue: a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles
@@ -278,84 +310,137 @@ def valu_issue(kernel_ms):
             "frac": floor_ms / kernel_ms}
 
 
-# the sources the headline final-stage kernel and its launch are built from
-# (the 2D Q^2 Euler instantiation, the shared device code and tables, the
-# launchers, the host code that maps tiles to workgroups, the ABI header)
-HEADLINE_SOURCES = ("include/crkdg.h", "paper_2412_16002_amd/csrc/device.hpp",
-                    "paper_2412_16002_amd/csrc/tables.hpp", "paper_2412_16002_amd/csrc/variants.hpp",
-                    "paper_2412_16002_amd/csrc/variants_v2d_q12_euler.hip",
-                    "paper_2412_16002_amd/csrc/host.hip")
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle as it stands, on independent sub-meshes of the
+# headline workload, one numpy thread per process
+# ---------------------------------------------------------------------------
+CPU_SAMPLE_N = 12
 
 
-def kernel_source_hash():
-    """Hash of the sources of the headline kernel, to tell whether committed
-    counter data still describe the kernel that runs."""
-    import hashlib
-    from pathlib import Path
-    h = hashlib.sha256()
-    for name in HEADLINE_SOURCES:
-        h.update(name.encode())
-        h.update((Path(ROOT) / name).read_bytes())
-    return h.hexdigest()[:16]
-
-
-def cpu_baseline(case, budget_s=20.0):
-    """The oracle, as it is, on a bounded sample of the same workload: a
-    periodic 96 x 96 sub-mesh with the same kind of data, one step at a time
-    until ~budget_s of CPU time, single thread."""
+def _cpu_worker(job):
+    seed, n, budget = job
     from threadpoolctl import threadpool_limits
 
     import oracle
     from paper_2412_16002_amd import inputs
     from tests._helpers import oracle_problem
 
-    n = 96
-    sub = inputs.euler_2d_voronoi(seed=0, n=n)
-    params = dict(case.params, n=(n, n))
+    case = inputs.euler_3d_wave(seed=seed, n=n)
     with threadpool_limits(limits=1):
-        o = oracle.CRKDG(oracle_problem(params))
-        U = o.constant_state(sub.cell_states)
-        U = o.limit(U)[0]
+        o = oracle.CRKDG(oracle_problem(case.params))
+        U = o.limit(o.project(case.u0))[0]
         t0 = time.perf_counter()
-        steps = 0
-        stages = 0
+        steps = stages = 0
         t = 0.0
-        while time.perf_counter() - t0 < budget_s or steps == 0:
+        while time.perf_counter() - t0 < budget or steps == 0:
             U, info = o.step(U, t)
             t = info["t"]
             steps += 1
             stages += o.p.stages * (info["halvings"] + 1)
         el = time.perf_counter() - t0
-    dof = o.ncell * o.M * o.V
-    return {"value": dof * stages / el, "unit": "DOF-stage updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"periodic {n}x{n} sub-mesh of the same 2D Euler Q2 Voronoi workload, "
-                      f"{steps} full steps in {el:.1f} s, FP64 numpy, 1 thread"}
+    return o.ncell * o.M * o.V * stages / el, steps, el
 
 
-def extra_workload(name, args, crkdg, inputs, torch, stream):
-    """Mixed and FP64 runs of one extra workload (step throughput, final-stage
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(budget_s=10.0):
+    """The oracle (FP64 numpy, unmodified) on periodic 12^3 sub-meshes of the
+    headline 3D workload: one process per host thread (at most 16, the CPU
+    share of one GPU), each on its own seeded sub-mesh, for ~budget_s, then
+    one process alone.  DOF-stage updates/s summed over the processes."""
+    import multiprocessing as mp
+    procs = max(1, min(16, os.cpu_count() or 1))
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(procs) as pool:
+        res = pool.map(_cpu_worker, [(s, CPU_SAMPLE_N, budget_s) for s in range(procs)])
+    with ctx.Pool(1) as pool:
+        one = pool.map(_cpu_worker, [(0, CPU_SAMPLE_N, budget_s)])[0]
+    value = sum(r[0] for r in res)
+    steps = sum(r[1] for r in res)
+    n = CPU_SAMPLE_N
+    return {"value": value, "unit": "DOF-stage updates/s", "cores": procs, "kind": "oracle",
+            "value_1thread": one[0], "cpu_model": _cpu_model(), "host_threads": os.cpu_count(),
+            "sample": f"{procs} processes (one numpy thread each), each on its own seeded periodic "
+                      f"{n}^3 sub-mesh of the 3D Euler Q2 RK4 density-wave workload, {steps} full steps "
+                      f"in ~{budget_s:.0f} s; then one process alone ({one[1]} steps): "
+                      f"FP64 oracle as it stands"}
+
+
+# ---------------------------------------------------------------------------
+# mixed vs FP64 at the same dt sequence
+# ---------------------------------------------------------------------------
+def equal_dt_l1(name, args, crkdg, inputs, torch, steps=10):
+    """Steps of the FP64 form with its own CFL steps, the same steps (dt
+    replayed per step) in the mixed form, from the same point samples;
+    relative L1 of the cell averages (max over variables) after each."""
+    runs = {}
+    dts = []
+    for prec in ("fp64", "mixed"):
+        _, mesh, slots, ctl = setup(name, prec, crkdg, inputs, torch, args.n, args.alpha)
+        for n in range(steps):
+            if prec == "mixed":
+                rec = mesh.ctl_read(ctl)[0]
+                rec["dt"] = rec["dt_fixed"] = dts[n]
+                mesh.ctl_write(ctl, [rec])
+            info = mesh.step(slots, ctl)[0]
+            if info["status"] != 0:
+                raise RuntimeError(f"{name} {prec}: status {info['status']} at step {n}")
+            if prec == "fp64":
+                dts.append(info["dt"])
+            elif info["dt"] != dts[n]:
+                raise RuntimeError(f"{name}: the mixed step {n} took dt {info['dt']}, not {dts[n]}")
+        runs[prec] = (mesh, slots, [c["cur"] for c in mesh.ctl_read(ctl)])
+    mf, sf, cf = runs["fp64"]
+    mm, sm, cm = runs["mixed"]
+    return {"steps": steps, "l1_rel_avg": l1_diff(mm, sm, cm, mf, sf, cf, torch), "t": sum(dts)}
+
+
+def summarise(name, r, args, mixed):
+    """JSON entry of one measured form of a workload."""
+    e = {"value": r["value"], "ms_per_step": r["ms"] / args.steps, "accepted_steps": r["accepted"],
+         "rejected_attempts": r["rejected"], "step_hbm_fraction": r["step_hbm_fraction"],
+         "tuning": r["tuning"]}
+    if name == "batched":
+        e["launch"] = "autotuned shapes; warm-up and timed attempts as two captured step graphs"
+    if "kern" in r:
+        e["kernel_ms"] = {f"stage{i}": v for i, v in r["kern"].items()}
+        f = r["final"]
+        e["final_stage_roofline"] = {"bound": "hbm", "achieved": f["achieved"], "peak": HBM_PEAK_GBS,
+                                     "unit": "GB/s", "frac": f["achieved"] / HBM_PEAK_GBS,
+                                     "alg_bytes_per_launch": f["alg_bytes"], "kernel_ms": f["kernel_ms"]}
+    return e
+
+
+def workload(name, args, crkdg, inputs, torch, stream):
+    """Mixed and FP64 runs of one workload (step throughput, final-stage
     roofline for single-instance meshes, mixed vs FP64 difference)."""
     out = {}
     finals = {}
-    for prec in ("mixed", "fp64"):
+    for prec in ("mixed",) + (() if args.no_fp64 else ("fp64",)):
         r, mesh, slots = measure(name, prec, args, crkdg, inputs, torch, stream, batched=(name == "batched"))
         finals[prec] = (mesh, slots, r["cur"])
-        e = {"value": r["value"], "ms_per_step": r["ms"] / args.steps, "accepted_steps": r["accepted"],
-             "rejected_attempts": r["rejected"], "step_hbm_fraction": r["step_hbm_fraction"]}
-        e["tuning"] = r["tuning"]
-        if name == "batched":
-            e["launch"] = "autotuned shapes; warm-up and timed attempts as two captured step graphs"
-        if "kern" in r:
-            e["kernel_ms"] = {f"stage{i}": v for i, v in r["kern"].items()}
-            f = r["final"]
-            e["final_stage_roofline"] = {"bound": "hbm", "achieved": f["achieved"], "peak": HBM_PEAK_GBS,
-                                         "unit": "GB/s", "frac": f["achieved"] / HBM_PEAK_GBS,
-                                         "alg_bytes_per_launch": f["alg_bytes"], "kernel_ms": f["kernel_ms"]}
-        out[prec] = e
-    out["speedup_mixed_vs_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
-    mm, sm, cm = finals["mixed"]
-    mf, sf, cf = finals["fp64"]
-    out["l1_rel_avg_mixed_vs_fp64"] = l1_diff(mm, sm, cm, mf, sf, cf, torch)
+        out[prec] = summarise(name, r, args, prec == "mixed")
+        out[prec]["_raw"] = r
+    if "fp64" in out:
+        out["speedup_mixed_vs_fp64"] = out["mixed"]["value"] / out["fp64"]["value"]
+        mm, sm, cm = finals["mixed"]
+        mf, sf, cf = finals["fp64"]
+        # after the same number of steps, each form with its own trial steps
+        out["l1_rel_avg_mixed_vs_fp64_own_dt"] = l1_diff(mm, sm, cm, mf, sf, cf, torch)
+    del finals
+    torch.cuda.empty_cache()
+    if "fp64" in out and name != "batched":
+        out["mixed_vs_fp64_equal_dt"] = equal_dt_l1(name, args, crkdg, inputs, torch)
+        torch.cuda.empty_cache()
     return out
 
 
@@ -367,6 +452,11 @@ def main():
                                    "per step) is not implemented",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
+    # the CPU baseline first, before anything touches the GPU (its worker
+    # processes start from a process without GPU state)
+    cpu = None
+    if not args.no_cpu and not args.only and not args.copy_calibration:
+        cpu = cpu_baseline(args.cpu_budget)
     import torch
 
     from paper_2412_16002_amd import crkdg, inputs
@@ -384,21 +474,19 @@ def main():
         return
     stream = torch.cuda.current_stream()
     if args.only:
-        print(json.dumps({args.only: extra_workload(args.only, args, crkdg, inputs, torch, stream)}), flush=True)
+        res = workload(args.only, args, crkdg, inputs, torch, stream)
+        for p in ("mixed", "fp64"):
+            if p in res:
+                res[p].pop("_raw")
+        print(json.dumps({args.only: res}), flush=True)
         return
-    Nc = args.n * args.n
-    M, V, s = 9, 4, 3
-    dof = Nc * M * V
 
-    results = {}
-    finals = {}
-    for prec in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):
-        r, mesh, slots = measure("euler2d", prec, args, crkdg, inputs, torch, stream)
-        results[prec] = r
-        finals[prec] = (mesh, slots, r["cur"])
-
-    mixed = results["mixed"]
+    head = workload("euler3d", args, crkdg, inputs, torch, stream)
+    mixed = head["mixed"].pop("_raw")
     fin = mixed["final"]
+    L = {"cells": 128 ** 3, "modes": 27, "vars": 5, "stages": 4}
+    dof = L["cells"] * L["modes"] * L["vars"]
+    S = state_bytes(L["vars"], L["modes"], True)
     line = {
         "metric": "DOF-stage updates/s (mixed vs FP64, same L1 error); % HBM roofline",
         "value": mixed["value"],
@@ -411,56 +499,60 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32+f64",
-        "data": "synthetic (seeded 64-site Voronoi states)",
-        "config": {"workload": f"2D Euler Q2 modal DG, {args.n}x{args.n} periodic, 3-stage cRKDG "
-                               f"(Heun3) + scaling limiter, mixed precision",
-                   "cells": Nc, "modes": M, "vars": V, "stages": s, "dof": dof, "lf_alpha": args.alpha},
+        "data": "synthetic (seeded smooth density wave, projected on the device)",
+        "config": {"workload": "3D Euler Q2 modal DG, 128^3 periodic, 4-stage cRKDG (RK4) + scaling "
+                               "limiter, mixed precision, smooth density wave rho = 1 + 0.99 sin",
+                   "dof": dof, "lf_alpha": args.alpha, **L},
         "accepted_steps": mixed["accepted"],
         "rejected_attempts": mixed["rejected"],
         "kernel_ms": {f"stage{i}": v for i, v in mixed["kern"].items()},
         "step_hbm_fraction": mixed["step_hbm_fraction"],
+        # the whole step against the HBM roofline: 13 state transfers of
+        # Scheme 1L with RK4 (2S + 3S + 3S + 5S)
+        "step_roofline": {"bound": "hbm", "alg_bytes_per_step": STEP_STATES[4] * S * L["cells"],
+                          "achieved": STEP_STATES[4] * S * L["cells"] / (mixed["ms"] / args.steps / 1e3) / 1e9,
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s"},
         "tuning": mixed["tuning"],
-        # dominant kernel: the final stage (reads u~^n and u~^(3), writes
-        # u~^{n+1}); its event time covers the stage kernel and the deferred
-        # limiter kernel that completes it (plus a ~2 us queue-counter reset)
+        # dominant kernel: the final stage (reads u~^n, u~^(2), u~^(3),
+        # u~^(4), writes u~^{n+1}: 5 S per cell); its event time covers the
+        # stage kernel and the deferred-limiter kernel that completes it
         "roofline": {"bound": "hbm", "achieved": fin["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": fin["achieved"] / HBM_PEAK_GBS,
                      "traffic": measured_traffic() if args.alpha == "face" else None,
-                     "kernel": "k_stage_final<2,2,Q,Euler,float> + k_limit_queue<...,final>",
+                     "kernel": "k_coop_stage<3,2,Euler,float,16,2,2,final> + k_limit_queue<...,final>",
                      "alg_bytes_per_launch": fin["alg_bytes"], "kernel_ms": fin["kernel_ms"]},
-        # the same launch against its VALU instruction-issue floor (the
-        # kernel is VALU-bound: the floor exceeds the HBM time of its bytes)
+        # the same launch against its VALU instruction-issue floor
         "valu": valu_issue(fin["kernel_ms"]) if args.alpha == "face" else None,
     }
-    if "fp64" in results:
-        f = results["fp64"]
-        line["fp64"] = {"value": f["value"], "ms_per_step": f["ms"] / args.steps,
-                        "kernel_ms": {f"stage{i}": v for i, v in f["kern"].items()},
-                        "accepted_steps": f["accepted"], "rejected_attempts": f["rejected"]}
-        line["speedup_mixed_vs_fp64"] = mixed["value"] / f["value"]
-        mm, sm, cm = finals["mixed"]
-        mf, sf, cf = finals["fp64"]
-        line["l1_rel_avg_mixed_vs_fp64"] = l1_diff(mm, sm, cm, mf, sf, cf, torch)
-        line["t_mixed_vs_fp64"] = [mixed["t"][0], f["t"][0]]
-    del finals
+    line["step_roofline"]["frac"] = line["step_roofline"]["achieved"] / HBM_PEAK_GBS
+    if "fp64" in head:
+        f = head["fp64"]
+        f.pop("_raw", None)
+        line["fp64"] = f
+        line["speedup_mixed_vs_fp64"] = head["speedup_mixed_vs_fp64"]
+        line["l1_rel_avg_mixed_vs_fp64_own_dt"] = head["l1_rel_avg_mixed_vs_fp64_own_dt"]
+        line["mixed_vs_fp64_equal_dt"] = head.get("mixed_vs_fp64_equal_dt")
     torch.cuda.empty_cache()
     extra = {}
     for name in [w for w in args.workloads.split(",") if w]:
         try:
-            extra[name] = extra_workload(name, args, crkdg, inputs, torch, stream)
+            extra[name] = workload(name, args, crkdg, inputs, torch, stream)
+            for p in ("mixed", "fp64"):
+                if p in extra[name]:
+                    extra[name][p].pop("_raw", None)
         except Exception as e:  # reported, never fatal to the headline line
             extra[name] = {"error": f"{type(e).__name__}: {e}", "trace": traceback.format_exc()[-600:]}
         torch.cuda.empty_cache()
-    rk = extra.get("euler2d_rkdg")
-    if rk and "error" not in rk:
+    rk, e2 = extra.get("euler2d_rkdg"), extra.get("euler2d")
+    if rk and e2 and "error" not in rk and "error" not in e2:
         # what compactness buys: cRKDG step time against standard RKDG's on
-        # the same workload, kernels and launch-shape tuning
-        rk["crkdg_speedup_over_rkdg"] = {p: rk[p]["ms_per_step"] / (results[p]["ms"] / args.steps)
-                                         for p in results}
+        # the same 2D workload, kernels and launch-shape tuning
+        rk["crkdg_speedup_over_rkdg"] = {p: rk[p]["ms_per_step"] / e2[p]["ms_per_step"]
+                                         for p in ("mixed", "fp64") if p in rk and p in e2}
     if extra:
         line["workloads"] = extra
-    if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(inputs.euler_2d_voronoi(seed=0, n=args.n))
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
 
 

@@ -94,8 +94,8 @@ extern "C" {
 #define CRKDG_ALPHA_GLOBAL 2 /* one alpha for every face: the wave-speed maximum a0 of Sec. 2.1,
                                max over d of crkdg_ctl.a0[d] (that of u~^n over S_K, which the
                                controller holds during a step; a caller of crkdg_stage sets it).
-                               Neither option is built for 3D Q^2 Euler or 2D P^3 Euler FP64:
-                               their init call returns CRKDG_E_UNSUPPORTED */
+                               Neither option is built for 2D P^3 Euler FP64:
+                               its init call returns CRKDG_E_UNSUPPORTED */
 
 #define CRKDG_FP64 0  /* every mode and all arithmetic in FP64 */
 #define CRKDG_MIXED 1 /* modes >= 1 and transforms/fluxes in FP32; averages,

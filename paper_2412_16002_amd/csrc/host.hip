@@ -161,6 +161,23 @@ void instance_tiles(const crkdg_problem& p, int inst, int threads, int tile_x, i
       }
 }
 
+// Tiles of tx x ty x tz cells (cooperative stage kernels), x fastest.
+void instance_tiles_3d(const crkdg_problem& p, int inst, const int* tile, int& lblock,
+                       std::vector<BlockItem>& out) {
+  const int n2 = (p.dim == 3) ? p.n[2] : 1;
+  for (int z = 0; z < n2; z += tile[2])
+    for (int y = 0; y < p.n[1]; y += tile[1])
+      for (int x = 0; x < p.n[0]; x += tile[0]) {
+        BlockItem it{};
+        it.inst = inst;
+        it.lblock = lblock++;
+        it.x0 = x;
+        it.y0 = y;
+        it.z = z;
+        out.push_back(it);
+      }
+}
+
 int64_t instance_tile_count(const crkdg_problem& p, int threads, int tile_x) {
   int64_t nc = 1;
   for (int d = 0; d < p.dim; ++d) nc *= p.n[d];
@@ -368,6 +385,14 @@ int ilog2(int x) {
 // 2D/3D tiles a power of two between 8 and the workgroup size wide; a
 // persistent grid a positive multiple of 8.
 int check_tune(const Group& g, const Tune& t) {
+  if (g.ops->coop) {
+    // one workgroup (one wavefront per variable) per tile of the variant's shape
+    if (t.threads != g.ops->coop || t.tile_x != g.ops->coop_tile[0] || t.grid != 0)
+      return fail(CRKDG_E_ARG, "this variant runs cooperative stage kernels: threads must be " +
+                                   std::to_string(g.ops->coop) + ", tile_x " +
+                                   std::to_string(g.ops->coop_tile[0]) + " and grid 0");
+    return CRKDG_OK;
+  }
   if (t.threads != 64 && t.threads != 128 && t.threads != 256)
     return fail(CRKDG_E_ARG, "threads must be 64, 128 or 256");
   if (g.dim == 1) {
@@ -387,7 +412,10 @@ int apply_tune(crkdg_mesh* m, int gi, const Tune& t) {
     return fail(CRKDG_E_ARG, "launch shapes are fixed while a step graph of the mesh exists");
   std::vector<BlockItem> logical;
   int lb = 0;
-  for (int i : g.insts) instance_tiles(m->probs[i], i, t.threads, t.tile_x, lb, logical);
+  for (int i : g.insts) {
+    if (g.ops->coop) instance_tiles_3d(m->probs[i], i, g.ops->coop_tile, lb, logical);
+    else instance_tiles(m->probs[i], i, t.threads, t.tile_x, lb, logical);
+  }
   std::vector<BlockItem> phys = xcd_block_map(logical);
   const int n = static_cast<int>(phys.size());
   if (n > g.smap_cap) {
@@ -468,11 +496,17 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
       delete m;
       return fail(CRKDG_E_UNSUPPORTED, "problem " + std::to_string(i) +
                                            ": the per-point and global Lax-Friedrichs alpha are not built "
-                                           "for this dim/k/space/system/precision (3D Q^2 Euler, 2D P^3 "
-                                           "Euler FP64)");
+                                           "for this dim/k/space/system/precision (2D P^3 Euler FP64)");
     }
     int64_t nc = 1;
     for (int d = 0; d < p.dim; ++d) nc *= p.n[d];
+    if (ops->coop && nc >= (int64_t(1) << 29)) {
+      // the cooperative kernels address a cell's row entries with 32-bit
+      // byte offsets (such a mesh would not fit in device memory anyway)
+      delete m;
+      return fail(CRKDG_E_UNSUPPORTED, "problem " + std::to_string(i) +
+                                           ": this variant takes fewer than 2^29 cells per instance");
+    }
     crkdg_instance_layout& L = m->lay[i];
     L.n_cells = nc;
     L.n_modes = ops->M;
@@ -582,6 +616,10 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
   for (size_t g = 0; g < m->groups.size(); ++g) {
     Tune t;
     if (m->groups[g].dim == 1) t.tile_x = t.threads;
+    if (m->groups[g].ops->coop) {
+      t.threads = m->groups[g].ops->coop;
+      t.tile_x = m->groups[g].ops->coop_tile[0];
+    }
     if (int rc = apply_tune(m, static_cast<int>(g), t)) {
       crkdg_free_mesh(m);
       return rc;
@@ -834,6 +872,18 @@ static int launch_stage(crkdg_mesh* m, int gi, int stage, const Slots& slots, cr
   const int qblocks = static_cast<int>(std::min<int64_t>(256, (g.ncells + BLOCK - 1) / BLOCK));
   const int grid = stage_grid(g);
   const bool persistent = grid < g.n_items;
+  if (g.ops->coop) {
+    if (stage <= g.stages) {
+      a.a = bt.a[stage];
+      (g.scheme == CRKDG_SCHEME_RKDG ? g.ops->coop_inner_dg : g.ops->coop_local)(a, g.n_items, g.ops->coop, s);
+      g.ops->queue_local(a, qblocks, BLOCK, s);
+    } else {
+      for (int j = 0; j < 4; ++j) a.b[j] = bt.b[j];
+      g.ops->coop_final(a, g.n_items, g.ops->coop, s);
+      g.ops->queue_final(a, qblocks, BLOCK, s);
+    }
+    return CRKDG_OK;
+  }
   if (stage <= g.stages) {
     a.a = bt.a[stage];
     if (g.scheme == CRKDG_SCHEME_RKDG)
@@ -986,6 +1036,14 @@ int group_pass(crkdg_mesh* m, int gi, const Slots& sl, crkdg_ctl* d_ctl, hipStre
 
 std::vector<Tune> candidates(const Group& g) {
   std::vector<Tune> out;
+  if (g.ops->coop) {
+    // the cooperative kernels have one launch shape per variant
+    Tune t;
+    t.threads = g.ops->coop;
+    t.tile_x = g.ops->coop_tile[0];
+    out.push_back(t);
+    return out;
+  }
   const int grids[] = {0, 1024, 2048};
   for (int th : {256, 128, 64}) {
     std::vector<int> widths;

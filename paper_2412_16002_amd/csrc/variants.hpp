@@ -2,6 +2,7 @@
 // (dimension, degree, space, system, precision).
 #pragma once
 
+#include "coop.hpp"
 #include "device.hpp"
 
 namespace crkdg {
@@ -18,6 +19,11 @@ struct VariantOps {
   Launch stage_local, stage_final, limit, cfl, project, queue_local, queue_final;
   Launch stage_local_p, stage_final_p;   // persistent-grid forms
   Launch stage_inner_dg, stage_inner_dg_p; // inner stage with F (standard RKDG)
+  // cooperative stage kernels (tensor spaces): one workgroup of 64 V threads
+  // per tile of coop_tile[0] x [1] x [2] cells; coop = 0 when not built
+  int coop;
+  int coop_tile[3];
+  Launch coop_local, coop_inner_dg, coop_final;
 };
 
 template <int D, int K, int SP, int SYS, typename T> struct Ops {
@@ -60,7 +66,33 @@ template <int D, int K, int SP, int SYS, typename T> struct Ops {
                       C::M, C::V, C::S::NQ, C::NS, static_cast<int>(sizeof(typename C::Record)), C::WALLS ? 1 : 0,
                       C::ALPHA_MODES ? 1 : 0,
                       &stage_local, &stage_final, &limit, &cfl, &project, &queue_local, &queue_final,
-                      &stage_local_p, &stage_final_p, &stage_inner_dg, &stage_inner_dg_p};
+                      &stage_local_p, &stage_final_p, &stage_inner_dg, &stage_inner_dg_p,
+                      0, {0, 0, 0}, nullptr, nullptr, nullptr};
+  }
+};
+
+// A variant whose stage kernels are the cooperative ones (tensor spaces, 2D
+// and 3D): every boundary kind and alpha mode is built in; the limiter,
+// wave-speed, projection and queue kernels stay the one-thread-per-cell ones.
+template <int D, int K, int SYS, typename T, int TX, int TY, int TZ> struct OpsCoop {
+  using B = Ops<D, K, SP_Q, SYS, T>;
+  static constexpr int NT = 64 * Phys<D, SYS>::V;
+  static void local(const KArgs& a, int nb, int, hipStream_t s) {
+    hipLaunchKernelGGL((k_coop_stage<D, K, SYS, T, TX, TY, TZ, 0>), dim3(nb), dim3(NT), 0, s, a);
+  }
+  static void inner_dg(const KArgs& a, int nb, int, hipStream_t s) {
+    hipLaunchKernelGGL((k_coop_stage<D, K, SYS, T, TX, TY, TZ, 1>), dim3(nb), dim3(NT), 0, s, a);
+  }
+  static void final_(const KArgs& a, int nb, int, hipStream_t s) {
+    hipLaunchKernelGGL((k_coop_stage<D, K, SYS, T, TX, TY, TZ, 2>), dim3(nb), dim3(NT), 0, s, a);
+  }
+  static VariantOps make() {
+    using C = Cell<D, K, SP_Q, SYS, T>;
+    return VariantOps{D, K, SP_Q, SYS, sizeof(T) == 8 ? CRKDG_FP64 : CRKDG_MIXED,
+                      C::M, C::V, C::S::NQ, C::NS, static_cast<int>(sizeof(typename C::Record)), 1, 1,
+                      nullptr, nullptr, &B::limit, &B::cfl, &B::project, &B::queue_local, &B::queue_final,
+                      nullptr, nullptr, nullptr, nullptr,
+                      NT, {TX, TY, TZ}, &local, &inner_dg, &final_};
   }
 };
 

@@ -1,10 +1,11 @@
-// Compiled variants: 3D Q^2 Euler (27 modes x 5 variables, rolled point
-// loops); FP64 and mixed precision.
+// Compiled variants: 3D Q^2 Euler (27 modes x 5 variables), FP64 and mixed
+// precision: cooperative stage kernels on 16 x 2 x 2 tiles; the limiter,
+// wave-speed and projection kernels one thread per cell (rolled point loops).
 #include "variants.hpp"
 
 namespace crkdg {
 static const VariantOps kOps[] = {
-    Ops<3, 2, SP_Q, SYS_EULER, double>::make(), Ops<3, 2, SP_Q, SYS_EULER, float>::make(),
+    OpsCoop<3, 2, SYS_EULER, double, 16, 2, 2>::make(), OpsCoop<3, 2, SYS_EULER, float, 16, 2, 2>::make(),
 };
 int variants_v3d_q2_euler(const VariantOps** out) {
   *out = kOps;
