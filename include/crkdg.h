@@ -269,6 +269,20 @@ int crkdg_limit(crkdg_mesh *mesh, crkdg_state u, crkdg_ctl *d_ctl, void *stream)
 int crkdg_cell_avg(crkdg_mesh *mesh, crkdg_state u, double *d_avg, double *d_totals,
                    void *stream);
 
+/* crkdg_cell_avg for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same averages and bitwise the same totals, with the per-block partial
+ * sums in a static device array of the library (1 MiB per GPU, held until
+ * the process ends) instead of the mesh's buffer.  Allocates nothing, frees
+ * nothing; the array's address is looked up once per device when a mesh is
+ * created on it.  Limit: meshes of at most 26214 blocks of 256 cells (about
+ * 6.7 million cells); larger ones are refused with CRKDG_E_ARG before any
+ * device work.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (different streams, host threads or meshes) race.
+ * Asynchronous. */
+int crkdg_cell_avg_noalloc(crkdg_mesh *mesh, crkdg_state u, double *d_avg, double *d_totals,
+                           void *stream);
+
 /* CFL wave-speed reduction (Sec. 2.1 definition of a0; Sec. 4.1 trial step):
  * d_ctl[inst].a0[d] = max over cells and S_K points of the largest |eigenvalue|
  * of df_d/du at u, and d_ctl[inst].dt = the trial step (or dt_fixed), clipped

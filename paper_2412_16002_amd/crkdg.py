@@ -93,6 +93,7 @@ def _load():
         "crkdg_project": (C.c_int, [C.c_void_p, C.c_void_p, CState, C.c_void_p]),
         "crkdg_limit": (C.c_int, [C.c_void_p, CState, C.c_void_p, C.c_void_p]),
         "crkdg_cell_avg": (C.c_int, [C.c_void_p, CState, C.c_void_p, C.c_void_p, C.c_void_p]),
+        "crkdg_cell_avg_noalloc": (C.c_int, [C.c_void_p, CState, C.c_void_p, C.c_void_p, C.c_void_p]),
         "crkdg_cfl": (C.c_int, [C.c_void_p, CState, C.c_void_p, C.c_void_p]),
         "crkdg_start": (C.c_int, [C.c_void_p, P(CState), C.c_int32, C.c_void_p, P(C.c_double),
                                   P(C.c_double), P(C.c_double), C.c_void_p]),
@@ -118,7 +119,8 @@ def _load():
 
 LIB = _load()
 EXPORTED = ("crkdg_last_error", "crkdg_init_mesh", "crkdg_free_mesh", "crkdg_instance_query",
-            "crkdg_points", "crkdg_project", "crkdg_limit", "crkdg_cell_avg", "crkdg_cfl",
+            "crkdg_points", "crkdg_project", "crkdg_limit", "crkdg_cell_avg", "crkdg_cell_avg_noalloc",
+            "crkdg_cfl",
             "crkdg_start", "crkdg_stage", "crkdg_step", "crkdg_group_count", "crkdg_get_tuning",
             "crkdg_set_tuning", "crkdg_autotune", "crkdg_graph_create", "crkdg_graph_launch",
             "crkdg_graph_destroy")
@@ -367,6 +369,13 @@ class Mesh:
         _check(LIB.crkdg_cell_avg(self.h, u.c(), None if avg is None else C.c_void_p(avg.data_ptr()),
                                   None if totals is None else C.c_void_p(totals.data_ptr()), _stream()),
                "crkdg_cell_avg")
+
+    def cell_avg_noalloc(self, u: State, avg=None, totals=None):
+        """crkdg_cell_avg_noalloc: the same results, partial sums in the
+        library's static device array (no allocation)."""
+        _check(LIB.crkdg_cell_avg_noalloc(self.h, u.c(), None if avg is None else C.c_void_p(avg.data_ptr()),
+                                          None if totals is None else C.c_void_p(totals.data_ptr()), _stream()),
+               "crkdg_cell_avg_noalloc")
 
     def totals(self, u: State):
         import torch

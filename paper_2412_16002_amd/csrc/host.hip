@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -22,6 +23,16 @@ using Registry = int (*)(const VariantOps**);
 const Registry kRegistries[] = {&variants_v1d, &variants_v2d_q_adv, &variants_v2d_p_adv, &variants_v2d_q12_euler, &variants_v2d_q3_euler, &variants_v2d_p_euler, &variants_v3d_q1, &variants_v3d_q2_adv, &variants_v3d_q2_euler, &variants_v3d_p, &variants_v3d_p2_euler};
 
 thread_local std::string g_err = "";
+
+// Partial sums of crkdg_cell_avg_noalloc (5 doubles per logical block of the
+// default tile map): file-scope device memory, one copy per GPU the library
+// runs on, held until the process ends.  Host code never uses the array's
+// name as an address: the device address comes from hipGetSymbolAddress,
+// once per device (in crkdg_init_mesh, with that device current).
+constexpr int64_t kScratchDoubles = int64_t(1) << 17;   // 1 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_ptr;   // device -> address of its scratch
 
 int fail(int code, const std::string& msg) {
   g_err = msg;
@@ -355,6 +366,24 @@ __global__ __launch_bounds__(BLOCK) void k_totals_final(const InstDev* inst, con
   }
 }
 
+// The device address of `scratch` on the current device `dev` (looked up
+// once per device; later calls return the stored address).
+int scratch_address(int dev, double** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return CRKDG_OK;
+  }
+  double* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(reinterpret_cast<void**>(&p), HIP_SYMBOL(scratch));
+  if (e != hipSuccess || p == nullptr)
+    return fail(CRKDG_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_ptr[dev] = p;
+  *out = p;
+  return CRKDG_OK;
+}
+
 int check_mesh(const crkdg_mesh* m) {
   if (!m) return fail(CRKDG_E_ARG, "mesh is NULL");
   return CRKDG_OK;
@@ -468,6 +497,14 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
   if (hipGetDevice(&m->device) != hipSuccess) {
     delete m;
     return fail(CRKDG_E_HIP, "hipGetDevice failed");
+  }
+  {
+    // set-up of the allocation-free totals: this device's scratch address
+    double* sp = nullptr;
+    if (int rc = scratch_address(m->device, &sp)) {
+      delete m;
+      return rc;
+    }
   }
   std::map<std::tuple<const VariantOps*, int, int>, int> gidx;
   int64_t avg_off = 0, hi_off = 0;
@@ -769,11 +806,9 @@ int crkdg_limit(crkdg_mesh* m, crkdg_state u, crkdg_ctl* d_ctl, void* stream) {
   return CRKDG_OK;
 }
 
-int crkdg_cell_avg(crkdg_mesh* m, crkdg_state u, double* d_avg, double* d_totals, void* stream) {
-  if (check_mesh(m)) return CRKDG_E_ARG;
-  if (!u.avg) return fail(CRKDG_E_ARG, "u.avg is NULL");
-  if (int rc = set_device(m)) return rc;
-  hipStream_t s = static_cast<hipStream_t>(stream);
+// averages and totals with the per-block partial sums in `partial`
+static int cell_avg_into(crkdg_mesh* m, crkdg_state u, double* d_avg, double* d_totals, double* partial,
+                         hipStream_t s) {
   if (d_avg)
     HIP_TRY(hipMemcpyAsync(d_avg, u.avg, sizeof(double) * m->layout.avg_elems, hipMemcpyDeviceToDevice, s));
   if (d_totals) {
@@ -781,19 +816,39 @@ int crkdg_cell_avg(crkdg_mesh* m, crkdg_state u, double* d_avg, double* d_totals
     for (const Group& g : m->groups) {
       const int V = g.ops->V;
       hipLaunchKernelGGL(k_totals_partial, dim3(g.nblocks), dim3(BLOCK), 0, s, m->d_inst, g.d_bmap,
-                         u.avg, m->d_partial, V);
+                         u.avg, partial, V);
     }
     HIP_TRY(hipGetLastError());
     // totals are packed per instance with that instance's V
     int64_t off = 0;
     for (int i = 0; i < m->layout.n_inst; ++i) {
-      hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(BLOCK), 0, s, m->d_inst + i, m->d_partial,
+      hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(BLOCK), 0, s, m->d_inst + i, partial,
                          d_totals + off, m->lay[i].n_vars);
       off += m->lay[i].n_vars;
     }
     HIP_TRY(hipGetLastError());
   }
   return CRKDG_OK;
+}
+
+int crkdg_cell_avg(crkdg_mesh* m, crkdg_state u, double* d_avg, double* d_totals, void* stream) {
+  if (check_mesh(m)) return CRKDG_E_ARG;
+  if (!u.avg) return fail(CRKDG_E_ARG, "u.avg is NULL");
+  if (int rc = set_device(m)) return rc;
+  return cell_avg_into(m, u, d_avg, d_totals, m->d_partial, static_cast<hipStream_t>(stream));
+}
+
+int crkdg_cell_avg_noalloc(crkdg_mesh* m, crkdg_state u, double* d_avg, double* d_totals, void* stream) {
+  if (check_mesh(m)) return CRKDG_E_ARG;
+  if (!u.avg) return fail(CRKDG_E_ARG, "u.avg is NULL");
+  if (static_cast<int64_t>(m->total_lblocks) * 5 > kScratchDoubles)
+    return fail(CRKDG_E_ARG, "crkdg_cell_avg_noalloc: the mesh has " + std::to_string(m->total_lblocks) +
+                                 " blocks of 256 cells; the static scratch holds partial sums of at most " +
+                                 std::to_string(kScratchDoubles / 5) + " (use crkdg_cell_avg)");
+  if (int rc = set_device(m)) return rc;
+  double* sp = nullptr;
+  if (int rc = scratch_address(m->device, &sp)) return rc;   // stored at mesh creation: no runtime call
+  return cell_avg_into(m, u, d_avg, d_totals, sp, static_cast<hipStream_t>(stream));
 }
 
 static int launch_cfl(crkdg_mesh* m, const crkdg_state* slots, int nslots, int rotate, crkdg_ctl* d_ctl,
