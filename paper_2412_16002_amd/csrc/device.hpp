@@ -354,6 +354,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
     }
   }
   __device__ __forceinline__ static void at_face(const State& s, int f, int b, T* u) {
+#pragma clang fp contract(off)
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       T a = T(s.ub[v]);
@@ -367,7 +368,11 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
   // spaces sum over the modes they have), then the 1D Legendre series at the
   // Gauss points of the tangential direction, whose nodes come in pairs +-y
   // (even and odd parts shared).  The same operations serve a cell's own
-  // trace and its neighbour's.
+  // trace and its neighbour's; floating-point contraction is off here (as in
+  // Phys), so that the two inlined copies -- the cell's own trace and the
+  // neighbour's view of it -- round alike and the face flux is bitwise the
+  // same in both cells (without it a lone product added to the even part
+  // was fused in one copy only: 2D P^1 mixed lost conservation at 1e-10).
   static constexpr bool SF = (D == 2) && !BIG;
   static constexpr int mode_of(int a, int b) {
     for (int m = 0; m < M; ++m)
@@ -386,6 +391,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
     return m == 0 ? T(s.ub[v]) : s.ch[v][m - 1];
   }
   __device__ __forceinline__ static void face_traces(const State& s, int f, T (&u)[S::NFP][V]) {
+#pragma clang fp contract(off)
     if constexpr (SF) {
       const int d = f / 2;
       const bool up = (f & 1) != 0;
@@ -699,6 +705,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
   // shared face.
   template <class GetAvg, class GetHi>
   __device__ __forceinline__ static void face_modes(GetAvg avg, GetHi get, int f, T (&R)[V][TM]) {
+#pragma clang fp contract(off)
     static_assert(S::TENSOR, "face_modes needs a tensor-product space");
     const int d = f / 2;
     const bool up = (f & 1) != 0;
@@ -727,6 +734,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
   }
   // trace value at face point b from the tangential coefficients
   __device__ __forceinline__ static void face_eval(const T (&R)[V][TM], int b, T* u) {
+#pragma clang fp contract(off)
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       T a = R[v][0];

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
-from _helpers import gpu_problem, oracle_problem, parity_tolerance, random_state, rel_err_per_var, round_hi
+from _helpers import gpu_problem, oracle_problem, limited_err, random_state, rel_err_per_var, round_hi
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -106,7 +106,7 @@ def test_boundary_stage_parity(lib, name):
         mesh.stage(i, states, out, ctl)
         got = mesh.get_legendre(out)
         c = mesh.ctl_read(ctl)[0]
-        err = float(np.max(np.abs(got - ref) / parity_tolerance(o, o.to_legendre(ref_u), ref, FP64_TOL)))
+        err = limited_err(o, o.to_legendre(ref_u), got, ref, FP64_TOL)
         _say(f"   error/tolerance {err:.2e} flags {c['flags']} oracle-admissible {ok_ref}")
         assert (c["flags"] == 0) == ok_ref
         assert err < 1.0

@@ -1,0 +1,132 @@
+"""The mixed-precision form against the FP64 oracle where FP32 rounding
+meets the limiter and the batch:
+
+* the limiter under heavy limiting (random modes three times the size
+  that keeps cells admissible) for every Euler family: averages untouched,
+  modes within the FP32 re-verification of the limiter (theta shrunk by at
+  most 2^-18 relative, reading A16) where theta is well conditioned, no
+  theta = 0 fallback where the oracle keeps a positive factor, and in the
+  cells whose density step pins rho at eps the limiter's defining property;
+* a batch of uneven smooth 2D instances (P^1-P^3, 3 or 4 stages) in the
+  mixed form, ten steps with the oracle's dt sequence replayed per
+  instance: relative L1 within 1e-6 of the oracle per instance (reading
+  A18), totals conserved in the FP64 averages."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from _helpers import (check_limiter_property, gpu_problem, l1_rel, oracle_problem, pinned_cells,
+                      random_state, round_hi)
+from paper_2412_16002_amd import inputs
+from test_gpu_parity import CASES
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+EULER = [n for n, p in CASES.items() if p["system"] == "euler"]
+EXTRA = {"euler3d_p2": dict(dim=3, n=(7, 6, 5), system="euler", k=2, space="P", stages=3, cfl=0.15)}
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2412_16002_amd import crkdg
+    return crkdg
+
+
+@pytest.mark.parametrize("name", EULER + list(EXTRA))
+def test_mixed_limit_parity(lib, name):
+    params = dict(CASES.get(name) or EXTRA[name], precision="mixed")
+    o = oracle.CRKDG(oracle_problem(params))
+    mesh = lib.Mesh(gpu_problem(params))
+    C = round_hi(random_state(o, seed=11, rel_amp=3.0, limited=False), "mixed")
+    ref = o.to_legendre(o.limit(o.from_legendre(C))[0])
+    u = mesh.new_state()
+    mesh.set_legendre(u, C)
+    ctl = mesh.new_ctl()
+    mesh.ctl_write(ctl, [{}])
+    mesh.limit(u, ctl)
+    got = mesh.get_legendre(u)
+    assert mesh.ctl_read(ctl)[0]["flags"] == 0
+    # the limiter never touches an average
+    assert np.array_equal(got[:, :, 0], C[:, :, 0])
+    limited = np.any(np.abs(ref[:, :, 1:] - C[:, :, 1:]) > 0, axis=(1, 2))
+    pinned = pinned_cells(o, C)
+    free = ~pinned
+    # where theta is well conditioned: the FP64 factor, shrunk by at most
+    # 2^-22 + 2^-18 when the FP32-rounded modes leave B^eps in FP64, then
+    # rounded to FP32
+    tol = 2.0 ** -17 * np.abs(ref) + 2.0 ** -23 * np.abs(C) + 1e-300
+    err = np.abs(got - ref) / tol
+    worst = float(np.max(err[free])) if free.any() else 0.0
+    # a theta = 0 fallback: every mode zeroed where the oracle keeps some
+    flat_gpu = np.all(got[:, :, 1:] == 0.0, axis=(1, 2))
+    flat_ref = np.all(np.abs(ref[:, :, 1:]) <= 1e-300, axis=(1, 2))
+    fallbacks = int(np.sum(flat_gpu & ~flat_ref & free))
+    _say(f"[mixed limit] {name}: limited {limited.mean():.2f}, pinned {pinned.sum()}, "
+         f"error/tol {worst:.2e}, theta=0 fallbacks {fallbacks}")
+    assert limited.mean() > 0.02
+    assert worst < 1.0
+    assert fallbacks == 0
+    check_limiter_property(o, C, got, pinned, rtol=1e-12, mixed=True)
+    assert o.bound_violations(o.from_legendre(got)) == 0
+
+
+BATCH = [(2, 24, "P", 3), (1, 30, "P", 3), (3, 12, "P", 4), (2, 17, "P", 3), (3, 9, "Q", 4)]
+
+
+def test_mixed_batch_against_the_oracle_with_its_dt(lib):
+    """Five uneven smooth instances in one mixed mesh (2D P^1-P^3 and Q^3,
+    3 or 4 stages): ten steps with the oracle's per-instance dt replayed
+    through the controllers; relative L1 (A18) of every instance within 1e-6
+    of the oracle's FP64 solution, totals conserved."""
+    cases = [inputs.euler_wave(2, (n, n), k, space=sp, stages=s, seed=i, amp=0.5, precision="mixed")
+             for i, (k, n, sp, s) in enumerate(BATCH)]
+    for cs in cases:
+        cs.params["cfl"] = {1: 0.3, 2: 0.15, 3: 0.09}[cs.params["k"]]
+    orcs = [oracle.CRKDG(oracle_problem(cs.params)) for cs in cases]
+    mesh = lib.Mesh([gpu_problem(cs.params) for cs in cases])
+    slots = mesh.new_slots()
+    Us = []
+    for i, (cs, o) in enumerate(zip(cases, orcs)):
+        C = round_hi(o.to_legendre(o.limit(o.project(cs.u0))[0]), "mixed")
+        Us.append(o.from_legendre(C))
+        mesh.set_legendre(slots[0], C, inst=i)
+    ctl = mesh.new_ctl()
+    mesh.start(slots, ctl)
+    tot0 = mesh.totals(slots[0]).cpu().numpy()
+    ts = [0.0] * len(cases)
+    for step in range(10):
+        dts = []
+        for i, o in enumerate(orcs):
+            Us[i], io = o.step(Us[i], ts[i])
+            ts[i] = io["t"]
+            dts.append(io["dt"])
+        recs = mesh.ctl_read(ctl)
+        for r, dt in zip(recs, dts):
+            r["dt"] = r["dt_fixed"] = dt
+        mesh.ctl_write(ctl, recs)
+        infos = mesh.step(slots, ctl)
+        for i, x in enumerate(infos):
+            assert x["status"] == 0 and x["dt"] == dts[i] and x["halvings"] == 0
+    for i, (o, x) in enumerate(zip(orcs, infos)):
+        got = mesh.get_legendre(slots[x["cur"]], inst=i)
+        err = l1_rel(o, got, o.to_legendre(Us[i]))
+        _say(f"[mixed batch] inst {i} k={o.k} {o.space} s={o.p.stages} N={o.n[0]} t={ts[i]:.3e} rel L1 {err:.2e}")
+        assert err < 1e-6
+        assert o.bound_violations(o.from_legendre(got)) == 0
+    tot = {c: mesh.totals(slots[c]).cpu().numpy() for c in {x["cur"] for x in infos}}
+    off = 0
+    for i, x in enumerate(infos):
+        V = mesh.inst[i]["n_vars"]
+        t1, t0 = tot[x["cur"]][off:off + V], tot0[off:off + V]
+        assert np.all(np.abs(t1 - t0) <= 1e-12 * np.abs(t0) + 1e-15), (i, t1, t0)
+        off += V

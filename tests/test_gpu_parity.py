@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
-from _helpers import (gpu_problem, oracle_problem, parity_tolerance, random_state, rel_err_per_var,
+from _helpers import (gpu_problem, oracle_problem, limited_err, random_state, rel_err_per_var,
                       round_hi)
 
 pytestmark = pytest.mark.gpu
@@ -82,8 +82,7 @@ def test_limit_parity(lib, name):
     mesh.limit(u, ctl)
     out = mesh.get_legendre(u)
     changed = np.mean(np.any(np.abs(ref - C) > 1e-12, axis=(1, 2)))
-    tol = parity_tolerance(o, C, ref)
-    err = float(np.max(np.abs(out - ref) / tol))
+    err = limited_err(o, C, out, ref)
     _say(f"   limited fraction {changed:.2f}, error / tolerance {err:.2e}")
     assert changed > 0.02
     assert err < 1.0
@@ -114,7 +113,7 @@ def test_stage_parity(lib, name):
         mesh.stage(i, states, out, ctl)
         got = mesh.get_legendre(out)
         c = mesh.ctl_read(ctl)[0]
-        err = float(np.max(np.abs(got - ref) / parity_tolerance(o, o.to_legendre(ref_u), ref, FP64_TOL)))
+        err = limited_err(o, o.to_legendre(ref_u), got, ref, FP64_TOL)
         _say(f"   error/tolerance {err:.2e} flags {c['flags']} oracle-admissible {ok_ref}")
         assert (c["flags"] == 0) == ok_ref
         assert err < 1.0
