@@ -239,6 +239,8 @@ struct Coop {
     else return __longlong_as_double(static_cast<long long>(b));
   }
 
+  // the LDS word type: indices into it stay 32-bit
+  using LT = __attribute__((address_space(3))) T;
   struct Smem {
     T buf[LDS_T];
     double avg[V][64];     // output averages of the tile's cells
@@ -252,23 +254,28 @@ struct Coop {
   // Element c of the row that starts at `row` (a wave-uniform address): the
   // byte offset is 32-bit (meshes of these variants hold fewer than 2^29
   // cells, checked at mesh creation), so the access is a scalar base plus
-  // one vector offset register
+  // one vector offset register.  Stores go through the global address space
+  // (vector memory instructions, not flat ones); loads stay generic, since
+  // global-space loads let the scheduler hoist the halo loads far ahead of
+  // their use and spill
   template <typename U>
-  __device__ __forceinline__ static U& at(U* row, uint32_t c) {
-    return *reinterpret_cast<U*>(reinterpret_cast<char*>(row) + c * static_cast<uint32_t>(sizeof(U)));
+  __device__ __forceinline__ static U ld(const U* row, uint32_t c) {
+    return *reinterpret_cast<const U*>(reinterpret_cast<const char*>(row) + c * static_cast<uint32_t>(sizeof(U)));
   }
   template <typename U>
-  __device__ __forceinline__ static const U& at(const U* row, uint32_t c) {
-    return *reinterpret_cast<const U*>(reinterpret_cast<const char*>(row) + c * static_cast<uint32_t>(sizeof(U)));
+  __device__ __forceinline__ static void st(U* row, uint32_t c, U x) {
+    using G = __attribute__((address_space(1))) char;
+    using GU = __attribute__((address_space(1))) U;
+    *(GU*)((G*)row + c * static_cast<uint32_t>(sizeof(U))) = x;
   }
   // modes of variable v (wave-uniform) of cell c in memory (mode 0 rounded to T)
   __device__ __forceinline__ static void load_var(const double* avg, const T* hi, int64_t nc, uint32_t c, int v,
                                                   T (&cm)[M], double& c0) {
-    c0 = at(avg + v * nc, c);
+    c0 = ld(avg + v * nc, c);
     cm[0] = T(c0);
     const T* h = hi + static_cast<int64_t>(v) * MH * nc;
 #pragma unroll
-    for (int m = 1; m < M; ++m) cm[m] = at(h + (m - 1) * nc, c);
+    for (int m = 1; m < M; ++m) cm[m] = ld(h + (m - 1) * nc, c);
   }
 
   // trace values of a cell on its two faces normal to d (tangential index
@@ -300,6 +307,9 @@ struct Coop {
       along<N, 2, 1>(tu, up, ev);
     }
   }
+
+  __device__ __forceinline__ static LT* lds(Smem& sm) { return (LT*)(sm.buf); }
+  __device__ __forceinline__ static const LT* lds(const Smem& sm) { return (const LT*)(sm.buf); }
 
   // tile geometry of the calling thread
   struct Geo {
@@ -362,11 +372,11 @@ struct Coop {
       along<N, D, 1>(t1, t2, ev);
       if constexpr (D == 2) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) sm.buf[(g.v * NQ + q) * 64 + g.lane] = t2[q];
+        for (int q = 0; q < NQ; ++q) lds(sm)[(g.v * NQ + q) * 64 + g.lane] = t2[q];
       } else {
         along<N, D, 2>(t2, t1, ev);
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) sm.buf[(g.v * NQ + q) * 64 + g.lane] = t1[q];
+        for (int q = 0; q < NQ; ++q) lds(sm)[(g.v * NQ + q) * 64 + g.lane] = t1[q];
       }
     }
     __syncthreads();
@@ -448,29 +458,47 @@ struct Coop {
   }
 
   // this variable's flux components (all directions, scaled by sd) at
-  // volume point q, from the point values of every variable in LDS
+  // volume point q, from the point values of every variable in LDS; the
+  // variable is uniform across the wavefront, so each wavefront takes one
+  // branch and forms only its own components
   __device__ __forceinline__ static void flux_at(const Geo& g, int q, const InstDev& I, const T (&sd)[D],
                                                  T (&fd)[D], const Smem& sm) {
     T u[V];
 #pragma unroll
-    for (int w = 0; w < V; ++w) u[w] = sm.buf[(w * NQ + q) * 64 + g.lane];
+    for (int w = 0; w < V; ++w) u[w] = lds(sm)[(w * NQ + q) * 64 + g.lane];
     if constexpr (SYS == SYS_EULER) {
       if (g.v == 0) {
+        // mass flux m_d
 #pragma unroll
         for (int d = 0; d < D; ++d) fd[d] = sd[d] * u[1 + d];
         return;
       }
-    }
-    const auto ax = P::aux(u, I);
+      const auto ax = P::aux(u, I);
+      if (g.v == D + 1) {
+        // energy flux (E + p) w_d
+        const T ep = u[D + 1] + ax.p;
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      T f[V];
-      P::flux(u, ax, d, I, f);
-      T x = f[0];
+        for (int d = 0; d < D; ++d) fd[d] = sd[d] * (ep * ax.w[d]);
+        return;
+      }
+      // momentum flux m_j w_d + p delta_jd, j = v - 1
+      static_for<D>([&](auto JJ) {
+        constexpr int j = decltype(JJ)::value;
+        if (g.v == 1 + j) {
 #pragma unroll
-      for (int w = 1; w < V; ++w)
-        if (g.v == w) x = f[w];
-      fd[d] = sd[d] * x;
+          for (int d = 0; d < D; ++d) {
+            const T x = u[1 + j] * ax.w[d];
+            fd[d] = sd[d] * ((j == d) ? x + ax.p : x);
+          }
+        }
+      });
+    } else {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+        T f[V];
+        P::flux(u, P::aux(u, I), d, I, f);
+        fd[d] = sd[d] * f[0];
+      }
     }
   }
 
@@ -495,8 +523,8 @@ struct Coop {
       traces<d>(cm, lo, up);
 #pragma unroll
       for (int b = 0; b < NFP; ++b) {
-        sm.buf[fidx<d>(g.v, b, 1, fi_lo)] = lo[b];
-        sm.buf[fidx<d>(g.v, b, 0, fi_up)] = up[b];
+        lds(sm)[fidx<d>(g.v, b, 1, fi_lo)] = lo[b];
+        lds(sm)[fidx<d>(g.v, b, 0, fi_up)] = up[b];
       }
     }
     if constexpr (DG) {
@@ -527,7 +555,7 @@ struct Coop {
         const int fi = slot<d>(p, h1, h2);
         // the halo cell below the tile shows its upper trace, the one above its lower trace
 #pragma unroll
-        for (int b = 0; b < NFP; ++b) sm.buf[fidx<d>(g.v, b, side, fi)] = side ? lo[b] : up[b];
+        for (int b = 0; b < NFP; ++b) lds(sm)[fidx<d>(g.v, b, side, fi)] = side ? lo[b] : up[b];
       }
     }
     __syncthreads();
@@ -576,7 +604,7 @@ struct Coop {
           const T ha = T(0.5) * ab;
 #pragma unroll
           for (int w = 0; w < V; ++w)
-            sm.buf[fidx<d>(w, b, 0, fi)] = fma(-ha, uR[w] - uL[w], T(0.5) * (fL[w] + fR[w]));
+            lds(sm)[fidx<d>(w, b, 0, fi)] = fma(-ha, uR[w] - uL[w], T(0.5) * (fL[w] + fR[w]));
         }
       }
     } else {
@@ -593,11 +621,11 @@ struct Coop {
         const int ss = side ? 0 : 1;
         T u[V];
 #pragma unroll
-        for (int w = 0; w < V; ++w) u[w] = sm.buf[fidx<d>(w, b, ss, fi)];
+        for (int w = 0; w < V; ++w) u[w] = lds(sm)[fidx<d>(w, b, ss, fi)];
         T fu[V];
         P::flux(u, P::aux(u, I), d, I, fu);
 #pragma unroll
-        for (int w = 0; w < V; ++w) sm.buf[fidx<d>(w, b, ss, fi)] = fu[w];
+        for (int w = 0; w < V; ++w) lds(sm)[fidx<d>(w, b, ss, fi)] = fu[w];
       }
     }
     __syncthreads();
@@ -607,8 +635,8 @@ struct Coop {
 #pragma unroll
       for (int b = 0; b < NFP; ++b) {
         // F: the face's flux (side 0 of the slot); G: the cell's own trace flux
-        flo[b] = sm.buf[fidx<d>(g.v, b, DG ? 0 : 1, fi_lo)];
-        fup[b] = sm.buf[fidx<d>(g.v, b, 0, fi_up)];
+        flo[b] = lds(sm)[fidx<d>(g.v, b, DG ? 0 : 1, fi_lo)];
+        fup[b] = lds(sm)[fidx<d>(g.v, b, 0, fi_up)];
       }
       const double sc = scale * I.rdx[d];
       // mode 0 in FP64, face by face in point order (the same sum in both cells)
@@ -666,10 +694,12 @@ struct Coop {
     if (p > g.A[d] || q1 >= g.A[oax1(d)] || (D == 3 && q2 >= g.A[oax2(d)])) return false;
     const bool ghost_lo = (p == 0) && (g.o[d] == 0) && I.bc[2 * d] != CRKDG_BC_PERIODIC;
     const bool ghost_up = (p == g.A[d]) && (g.o[d] + p == I.n[d]) && I.bc[2 * d + 1] != CRKDG_BC_PERIODIC;
+    // both sides read unconditionally (a ghost side's slot holds stale
+    // words, overwritten below)
 #pragma unroll
     for (int w = 0; w < V; ++w) {
-      uL[w] = ghost_lo ? T(0) : sm.buf[fidx<d>(w, b, 0, fi)];
-      uR[w] = ghost_up ? T(0) : sm.buf[fidx<d>(w, b, 1, fi)];
+      uL[w] = lds(sm)[fidx<d>(w, b, 0, fi)];
+      uR[w] = lds(sm)[fidx<d>(w, b, 1, fi)];
     }
     if (ghost_lo) ghost(2 * d, I, uR, uL);
     if (ghost_up) ghost(2 * d + 1, I, uL, uR);
@@ -718,7 +748,7 @@ struct Coop {
         for (int a = 0; a < N; ++a) line[a] = t[fam == 0 ? a + N * b : b + N * a];
         O1::eval_l(line, lv);
 #pragma unroll
-        for (int l = 0; l < NL; ++l) sm.buf[(g.v * NPF + l + NL * b) * 64 + g.lane] = lv[l];
+        for (int l = 0; l < NL; ++l) lds(sm)[(g.v * NPF + l + NL * b) * 64 + g.lane] = lv[l];
       }
       (void)u;
     } else {
@@ -732,7 +762,7 @@ struct Coop {
         for (int a = 0; a < N; ++a) line[a] = u[(b % N) * s1 + (b / N) * s2 + a * sf];
         O1::eval_l(line, lv);
 #pragma unroll
-        for (int l = 0; l < NL; ++l) sm.buf[(g.v * NPF + l + NL * b) * 64 + g.lane] = lv[l];
+        for (int l = 0; l < NL; ++l) lds(sm)[(g.v * NPF + l + NL * b) * 64 + g.lane] = lv[l];
       }
     }
   }
@@ -743,11 +773,17 @@ struct Coop {
                                              Smem& sm) {
     const Geo g = geo(bi, I, threadIdx.x);
     const int s = I.stages;
-    const int cur = a.slots.rotate ? ctl->cur : 0;
+    // the controller's fields this kernel reads, none of which it writes:
+    // scalar loads (constant address space)
+    using CC = const __attribute__((address_space(4))) crkdg_ctl;
+    const CC* cc = (const CC*)ctl;
+    const int cur = a.slots.rotate ? cc->cur : 0;
     const int nsl = s + 1;
     const int64_t nc = I.ncell;
-    const double dt = ctl->dt;
-    const double ag = CellT::global_alpha(ctl);
+    const double dt = cc->dt;
+    double ag = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) ag = fmax(ag, cc->a0[d]);   // the global alpha (Sec. 2.1 a0)
     T r[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) r[m] = T(0);
@@ -886,7 +922,7 @@ struct Coop {
           for (int p = g.v; p < NPF; p += V) {
             T u[V];
 #pragma unroll
-            for (int w = 0; w < V; ++w) u[w] = sm.buf[(w * NPF + p) * 64 + g.lane];
+            for (int w = 0; w < V; ++w) u[w] = lds(sm)[(w * NPF + p) * 64 + g.lane];
             check(u);
           }
         }
@@ -905,10 +941,10 @@ struct Coop {
     T* o_hi = hi_ptr<T>(sel_hi(a.slots, sl_out), I.hi_off);
     const int64_t nc = I.ncell;
     if (g.active && !queue) {
-      at(o_avg + g.v * nc, g.c) = o0;
+      st(o_avg + g.v * nc, g.c, o0);
       T* h = o_hi + static_cast<int64_t>(g.v) * MH * nc;
 #pragma unroll
-      for (int m = 1; m < M; ++m) at(h + (m - 1) * nc, g.c) = oc[m];
+      for (int m = 1; m < M; ++m) st(h + (m - 1) * nc, g.c, oc[m]);
     }
     // queued cells: one record each, limited by the queue kernel
     if (g.v == 0 && queue) sm.qidx[g.lane] = atomicAdd(a.qcount, 1u);
@@ -987,11 +1023,26 @@ __global__ __launch_bounds__((64 * Phys<D, SYS>::V)) __attribute__((amdgpu_waves
   using C = Coop<D, K, SYS, T, TX, TY, TZ>;
   __shared__ typename C::Smem sm;
   if (static_cast<int>(blockIdx.x) >= a.n_items) return;
-  const BlockItem bi = a.bmap[blockIdx.x];
+  // the tile, the instance's constants and the controller's state are
+  // uniform and read-only here: scalar loads (constant address space)
+  using CB = const __attribute__((address_space(4))) BlockItem;
+  using CI = const __attribute__((address_space(4))) InstDev;
+  using CC = const __attribute__((address_space(4))) crkdg_ctl;
+  const CB* pb = (const CB*)a.bmap + blockIdx.x;
+  BlockItem bi;
+  bi.inst = pb->inst;
+  bi.lblock = pb->lblock;
+  bi.x0 = pb->x0;
+  bi.y0 = pb->y0;
+  bi.z = pb->z;
+  bi.pad = 0;
   if (bi.inst < 0) return;  // padding entry of the XCD-ordered block map
-  const InstDev& I = a.inst[bi.inst];
+  // the instance's constants, read where used through the constant address
+  // space (scalar loads)
+  const InstDev& I = *(const InstDev*)((const CI*)a.inst + bi.inst);
   crkdg_ctl* ctl = a.ctl + bi.inst;
-  if (instance_idle(ctl)) return;
+  const CC* cc = (const CC*)ctl;
+  if (cc->status != 0 || cc->accepted >= cc->goal) return;   // instance idle
   C::template run<KIND>(a, bi, I, ctl, sm);
 }
 
