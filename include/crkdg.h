@@ -252,6 +252,25 @@ int crkdg_points(const crkdg_mesh *mesh, int32_t inst, int32_t which, double *xy
  * Thm. 3.5, assumes a limited u^0). */
 int crkdg_project(crkdg_mesh *mesh, const double *d_samples, crkdg_state out, void *stream);
 
+/* Source term (right-hand side) of every instance, for the manufactured
+ * solutions of the accuracy tests (Sec. 4.2, Example 4.2 scenario I):
+ *   s(x, t) = sum_{p < n_terms} exp(-rate_p t) cos(omega_p t + phase_p) S_p(x),
+ * with coef[3 p + 0..2] = (rate_p, omega_p, phase_p) (host array) and S_p
+ * given as the modal state terms[p] (the mesh's layout and precision, e.g.
+ * the crkdg_project of S_p's volume Gauss-point values; an instance without
+ * a source holds zeros there).  Each operator value of a stage gains the
+ * source at the time of the stage value it is applied to, t^n + c_j dt with
+ * c_j the Butcher table's stage times: dt a_{i,i-1} g(t^n + c_{i-1} dt) S in
+ * inner stage i, dt sum_j b_j g(t^n + c_j dt) S in the final stage.  The
+ * mesh keeps the pointers (caller-owned device memory that must stay valid
+ * while the mesh steps); n_terms = 0 removes the source.  At most
+ * CRKDG_MAX_SOURCE_TERMS terms; refused (CRKDG_E_ARG) while step graphs of
+ * the mesh exist, since they hold the previous source.  A source breaks
+ * conservation by design, and the bound-preservation theorem does not cover
+ * it: the halving of Sec. 4.1 still guards every stage average. */
+#define CRKDG_MAX_SOURCE_TERMS 4
+int crkdg_set_source(crkdg_mesh *mesh, int32_t n_terms, const crkdg_state *terms, const double *coef);
+
 /* Scaling limiter in place (Prop. 2.4 scalar; Sec. 2.2.3 Euler).  Cell
  * averages are unchanged.  Cells whose average is outside B / B^eps raise
  * CRKDG_F_AVERAGE in d_ctl[inst].flags (theta is then clamped to [0,1]).

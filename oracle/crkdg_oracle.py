@@ -67,6 +67,10 @@ design notes of the repository):
       |m|, |M|) of B (round-off at a bound the data attain); the limiter then
       flattens such a cell to its average.  Euler checks are exact (B^eps
       already keeps a margin to positivity).
+  A25 a source term s(x, t) (the manufactured solutions of Sec. 4.2) enters
+      both operators as its L2 projection (the volume Gauss rule) at the time
+      of the stage value it is paired with: G(u, t) = -div^loc f(u) + P s(t),
+      F likewise, with u~^(j) at t^n + c_j dt, c_j = sum_k a_jk.
 """
 from __future__ import annotations
 
@@ -205,6 +209,7 @@ class Problem:
     max_halvings: int = 40
     limiter: bool = True
     alpha: str = "face"           # LF alpha per face (A1), per face point, or global
+    source: object = None         # s(X[..., d], t) -> [..., V]: right-hand side (A25)
 
     @property
     def nvars(self):
@@ -628,12 +633,21 @@ class CRKDG:
         a = self.a0(U)
         return self.p.cfl / np.sum(a / self.dx)
 
-    def stage(self, i, Un, tilde, dt, op=None):
+    def source_term(self, t):
+        """P s(t): the L2 projection of the source at time t (A25), or None."""
+        if self.p.source is None:
+            return None
+        return self.project(lambda X: self.p.source(X, t))
+
+    def stage(self, i, Un, tilde, dt, op=None, t=0.0):
         """Un-limited stage i (2..s) or the final stage (i = s+1) of Scheme 1L:
         u^(i) = u~^n + dt sum_j a_ij G(u~^(j)),  u^{n+1} = u~^n + dt sum_i b_i F(u~^(i)).
         `tilde` is the list [u~^(1) = u~^n, u~^(2), ...].  `op` overrides the
-        operator of the inner stages (standard RKDG uses F everywhere)."""
+        operator of the inner stages (standard RKDG uses F everywhere).  With
+        a source, each operator value gains P s at its stage time (A25); t is
+        the time of u~^n."""
         A, b = BUTCHER[self.p.stages]
+        c = A.sum(axis=1)
         s = self.p.stages
         out = Un.copy()
         F = self.F
@@ -642,23 +656,29 @@ class CRKDG:
 
             def F(V):
                 return self.F(V, a_glob=ag)
+
+        def with_source(value, j):
+            src = self.source_term(t + c[j - 1] * dt)
+            return value if src is None else value + src
+
         if i <= s:
             inner = self.G if op is None else (F if op == self.F else op)
             for j in range(1, i):
                 if A[i - 1, j - 1] != 0.0:
-                    out = out + dt * A[i - 1, j - 1] * inner(tilde[j - 1])
+                    out = out + dt * A[i - 1, j - 1] * with_source(inner(tilde[j - 1]), j)
         else:
             for j in range(1, s + 1):
                 if b[j - 1] != 0.0:
-                    out = out + dt * b[j - 1] * F(tilde[j - 1])
+                    out = out + dt * b[j - 1] * with_source(F(tilde[j - 1]), j)
         return out
 
-    def attempt(self, Un, dt, op=None):
-        """One step attempt from the limited u~^n.  Returns (u~^{n+1}, ok)."""
+    def attempt(self, Un, dt, op=None, t=0.0):
+        """One step attempt from the limited u~^n at time t.  Returns
+        (u~^{n+1}, ok)."""
         s = self.p.stages
         tilde = [Un]
         for i in range(2, s + 2):
-            u = self.stage(i, Un, tilde, dt, op)
+            u = self.stage(i, Un, tilde, dt, op, t)
             if not np.all(self.admissible_average(self.cell_average(u))):
                 return None, False
             tilde.append(self.limit(u)[0])
@@ -671,7 +691,7 @@ class CRKDG:
         dt = min(dt, t_end - t)
         halvings = 0
         while True:
-            out, ok = self.attempt(Un, dt, op)
+            out, ok = self.attempt(Un, dt, op, t)
             if ok:
                 return out, dict(dt=dt, halvings=halvings, t=t + dt)
             halvings += 1

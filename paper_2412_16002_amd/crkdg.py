@@ -92,6 +92,7 @@ def _load():
                                    P(C.c_int32)]),
         "crkdg_project": (C.c_int, [C.c_void_p, C.c_void_p, CState, C.c_void_p]),
         "crkdg_limit": (C.c_int, [C.c_void_p, CState, C.c_void_p, C.c_void_p]),
+        "crkdg_set_source": (C.c_int, [C.c_void_p, C.c_int32, P(CState), P(C.c_double)]),
         "crkdg_cell_avg": (C.c_int, [C.c_void_p, CState, C.c_void_p, C.c_void_p, C.c_void_p]),
         "crkdg_cell_avg_noalloc": (C.c_int, [C.c_void_p, CState, C.c_void_p, C.c_void_p, C.c_void_p]),
         "crkdg_cfl": (C.c_int, [C.c_void_p, CState, C.c_void_p, C.c_void_p]),
@@ -119,7 +120,8 @@ def _load():
 
 LIB = _load()
 EXPORTED = ("crkdg_last_error", "crkdg_init_mesh", "crkdg_free_mesh", "crkdg_instance_query",
-            "crkdg_points", "crkdg_project", "crkdg_limit", "crkdg_cell_avg", "crkdg_cell_avg_noalloc",
+            "crkdg_points", "crkdg_project", "crkdg_limit", "crkdg_set_source", "crkdg_cell_avg",
+            "crkdg_cell_avg_noalloc",
             "crkdg_cfl",
             "crkdg_start", "crkdg_stage", "crkdg_step", "crkdg_group_count", "crkdg_get_tuning",
             "crkdg_set_tuning", "crkdg_autotune", "crkdg_graph_create", "crkdg_graph_launch",
@@ -360,6 +362,20 @@ class Mesh:
     def project(self, samples, out: State):
         _check(LIB.crkdg_project(self.h, C.c_void_p(samples.data_ptr()), out.c(), _stream()),
                "crkdg_project")
+
+    def set_source(self, terms, coef):
+        """crkdg_set_source: s(x, t) = sum_p exp(-rate_p t) cos(omega_p t +
+        phase_p) S_p(x) with S_p the states `terms` and coef a list of
+        (rate, omega, phase) triples; the states stay referenced by the mesh
+        (kept alive here too).  Empty lists remove the source."""
+        n = len(terms)
+        flat = [float(x) for c in coef for x in c]
+        if len(flat) != 3 * n:
+            raise ValueError("one (rate, omega, phase) triple per term")
+        cs = (CState * max(n, 1))(*[t.c() for t in terms])
+        cf = (C.c_double * max(3 * n, 1))(*flat)
+        _check(LIB.crkdg_set_source(self.h, n, cs, cf), "crkdg_set_source")
+        self._source_terms = list(terms)
 
     def limit(self, u: State, ctl=None):
         _check(LIB.crkdg_limit(self.h, u.c(), None if ctl is None else C.c_void_p(ctl.data_ptr()),

@@ -768,6 +768,21 @@ struct Coop {
   }
 
   // ---- a stage: inner (KIND 0: G, KIND 1: F) or final (KIND 2)
+  // r0, r += sum_p kap_p S_p for this thread's variable and cell
+  __device__ __forceinline__ static void add_source(const KArgs& a, const BlockItem& bi, const InstDev& I,
+                                                    const Geo& g, T (&r)[M], double& r0) {
+    const double* kap = source_weights(a, bi.inst);
+    const int64_t nc = I.ncell;
+#pragma unroll 1
+    for (int p = 0; p < a.src.n; ++p) {
+      r0 = fma(kap[p], ld(a.src.avg[p] + I.avg_off + g.v * nc, g.c), r0);
+      const T kt = T(kap[p]);
+      const T* h = static_cast<const T*>(a.src.hi[p]) + I.hi_off + static_cast<int64_t>(g.v) * MH * nc;
+#pragma unroll
+      for (int m = 1; m < M; ++m) r[m] = fma(kt, ld(h + (m - 1) * nc, g.c), r[m]);
+    }
+  }
+
   template <int KIND>
   __device__ __forceinline__ static void run(const KArgs& a, const BlockItem& bi, const InstDev& I, crkdg_ctl* ctl,
                                              Smem& sm) {
@@ -788,6 +803,13 @@ struct Coop {
 #pragma unroll
     for (int m = 0; m < M; ++m) r[m] = T(0);
     double r0 = 0.0;
+    // the stage's source terms sum_p kap_p S_p: in the final stage they seed
+    // the accumulator (before the four F, while nothing else holds
+    // registers), in an inner stage they join it after the operator (a
+    // seeded accumulator stays live through the operator and spills there)
+    if constexpr (KIND == 2) {
+      if (a.src.n > 0 && g.active) add_source(a, bi, I, g, r, r0);
+    }
     int sl_out;
     if constexpr (KIND == 2) {
       sl_out = (cur + s) % nsl;
@@ -812,6 +834,9 @@ struct Coop {
       const double* in_avg = sel_avg(a.slots, sl_in) + I.avg_off;
       const T* in_hi = hi_ptr<T>(sel_hi(a.slots, sl_in), I.hi_off);
       op<KIND == 1>(g, in_avg, in_hi, I, dt * a.a, ag, r, r0, sm);
+    }
+    if constexpr (KIND != 2) {
+      if (a.src.n > 0 && g.active) add_source(a, bi, I, g, r, r0);
     }
     // out = u~^n + r
     const double* b_avg = sel_avg(a.slots, cur) + I.avg_off;
@@ -1008,11 +1033,13 @@ struct Coop {
 // (measured on the 3D Q^2 Euler workload): the mixed final stage at 4 (128
 // VGPRs, a few spilled: three workgroups per CU) runs 20% faster than
 // unconstrained, the mixed inner stages at 5 (96 VGPRs: four workgroups per
-// CU) 13% faster than at 4; the FP64 kernels stay unconstrained (their LDS
-// limits them to two workgroups per CU).
+// CU) 13% faster than at 4; the inner stage with F (standard RKDG) needs the
+// final stage's budget (at 96 VGPRs its Lax--Friedrichs pass spills
+// kilobytes per lane); the FP64 kernels stay unconstrained (their LDS limits
+// them to two workgroups per CU).
 template <typename T, int KIND>
 constexpr int coop_waves_per_eu() {
-  return (sizeof(T) == 4) ? (KIND == 2 ? 4 : 5) : 1;
+  return (sizeof(T) == 4) ? (KIND == 0 ? 5 : 4) : 1;
 }
 
 // One workgroup (one wavefront per variable) per tile of the stage map.

@@ -94,6 +94,21 @@ struct Slots {
   int32_t rotate;    // 1: slot of u~^n is ctl->cur (step ring); 0: slot 0
 };
 
+// A source term s(x, t) = sum_p g_p(t) S_p(x) with g_p(t) = exp(-rate_p t)
+// cos(omega_p t + phase_p): the S_p as modal states (their L2 projections,
+// the mesh's layout and precision).  The manufactured solutions of the
+// accuracy tests (Sec. 4.2) have sources of this form.
+constexpr int MAX_SRC = CRKDG_MAX_SOURCE_TERMS;
+constexpr int SRC_STAGES = 8;   // weight rows per instance, indexed by stage number
+struct Src {
+  const double* avg[MAX_SRC];
+  const void* hi[MAX_SRC];
+  double rate[MAX_SRC], omega[MAX_SRC], phase[MAX_SRC];
+  double* w;         // [instance][SRC_STAGES][MAX_SRC] weights of the terms per stage
+  int32_t n;         // 0: no source
+  int32_t pad;
+};
+
 struct KArgs {
   const InstDev* inst;
   const BlockItem* bmap;
@@ -110,6 +125,8 @@ struct KArgs {
   unsigned qcap;       // record capacity of the queue (cells of the group)
   int32_t n_items;     // entries of bmap
   int32_t tile_shift;  // log2 of the tile width (2D/3D)
+  double c[4];         // stage times c_1..c_s of the Butcher table (fractions of dt)
+  Src src;
 };
 
 // ---------------------------------------------------------------------------
@@ -136,6 +153,16 @@ __device__ __forceinline__ void* sel_hi(const Slots& s, int i) {
   for (int k = 1; k < MAX_SLOTS; ++k)
     if (i == k) p = s.hi[k];
   return p;
+}
+
+// The weight of each source term in a stage (the source paired with the
+// stage values as the operators are, Sec. 4.2): dt a_{i,i-1} g_p(t^n +
+// c_{i-1} dt) in inner stage i, dt sum_j b_j g_p(t^n + c_j dt) in the final
+// stage; written per instance by a one-thread-per-instance kernel before the
+// stage (the stage kernels only read them: the transcendental calls stay out
+// of their register budget).
+__device__ __forceinline__ const double* source_weights(const KArgs& a, int inst) {
+  return a.src.w + (static_cast<int64_t>(inst) * SRC_STAGES + a.stage) * MAX_SRC;
 }
 
 __device__ __forceinline__ bool instance_idle(const crkdg_ctl* c) {
@@ -992,6 +1019,24 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
     }
   }
 
+  // out += sum_p kap_p S_p (mode 0 in FP64, the other modes in T)
+  __device__ __forceinline__ static void add_source(const KArgs& a, const InstDev& I, int64_t c,
+                                                    const double* kap, State& out) {
+    const int64_t nc = I.ncell;
+    for (int p = 0; p < a.src.n; ++p) {
+      const double* sa = a.src.avg[p] + I.avg_off;
+      const T* sh = static_cast<const T*>(a.src.hi[p]) + I.hi_off;
+      const T kt = T(kap[p]);
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        out.ub[v] = fma(kap[p], sa[v * nc + c], out.ub[v]);
+#pragma unroll
+        for (int m = 0; m < MH; ++m)
+          out.ch[v][m] = fma(kt, sh[(static_cast<int64_t>(v) * MH + m) * nc + c], out.ch[v][m]);
+      }
+    }
+  }
+
   // admissibility of the cell average (Sec. 4.1 algorithm; B^eps by reading A6)
   __device__ __forceinline__ static bool average_ok(const State& s, const InstDev& I) {
     if constexpr (SYS == SYS_EULER) {
@@ -1385,6 +1430,7 @@ __device__ __forceinline__ void stage_local_item(const KArgs& a, const BlockItem
     typename C::State base, out;
     C::load(b_avg, b_hi, I.ncell, c, base);
     C::combine(base, r, out);
+    if (a.src.n > 0) C::add_source(a, I, c, source_weights(a, bi.inst), out);
     bad = !C::average_ok(out, I);
     nonfin = !C::average_finite(out);
     const bool pass = !I.limiter || C::interval_pass(out, I) || C::template sk_pass<false>(out, I, nullptr);
@@ -1463,6 +1509,7 @@ __device__ __forceinline__ void stage_final_item(const KArgs& a, const BlockItem
     C::load(b_avg, b_hi, I.ncell, c, base);
     typename C::State out;
     C::combine(base, r, out);
+    if (a.src.n > 0) C::add_source(a, I, c, source_weights(a, bi.inst), out);
     bad = !C::average_ok(out, I);
     nonfin = !C::average_finite(out);
     double sp[D];

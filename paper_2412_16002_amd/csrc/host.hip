@@ -124,6 +124,8 @@ struct crkdg_mesh {
   int max_stages = 0;
   int device = 0;
   int live_graphs = 0;          // step graphs holding this mesh's stage maps
+  Src src{};                    // source term (crkdg_set_source)
+  double* d_srcw = nullptr;     // its per-stage weights [instance][SRC_STAGES][MAX_SRC]
 };
 
 namespace {
@@ -255,6 +257,38 @@ int validate(const crkdg_problem& p, int idx) {
 __global__ void k_zero_u32(unsigned* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
+}
+
+// Weights of the source terms in stage `stage` of every instance with
+// `stages` stages, from its controller's t^n and dt: dt a_{i,i-1} g_p(t^n +
+// c_{i-1} dt) in an inner stage i, dt sum_j b_j g_p(t^n + c_j dt) in the final
+// stage, g_p(t) = exp(-rate_p t) cos(omega_p t + phase_p).  One thread per
+// instance; idle instances are skipped as the stage kernels skip them.
+struct StageCoef {
+  double a;      // a_{stage, stage-1}
+  double b[4];
+  double c[4];   // stage times c_1..c_s
+};
+__global__ void k_source_weights(const InstDev* inst, const crkdg_ctl* ctl, int n, int stages, int stage,
+                                 StageCoef sc, Src src) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || inst[i].stages != stages || instance_idle(ctl + i)) return;
+  const double t = ctl[i].t, dt = ctl[i].dt;
+  double* w = src.w + (static_cast<int64_t>(i) * SRC_STAGES + stage) * MAX_SRC;
+  for (int p = 0; p < src.n; ++p) {
+    auto g = [&](double cj) {
+      const double tj = t + cj * dt;
+      return exp(-src.rate[p] * tj) * cos(fma(src.omega[p], tj, src.phase[p]));
+    };
+    double k = 0.0;
+    if (stage > stages) {
+      for (int j = 0; j < stages; ++j)
+        if (sc.b[j] != 0.0) k += sc.b[j] * g(sc.c[j]);
+    } else {
+      k = sc.a * g(sc.c[stage - 2]);
+    }
+    w[p] = dt * k;
+  }
 }
 
 __global__ void k_controller(crkdg_ctl* ctl, const InstDev* inst, int n, unsigned* qcount, int nq) {
@@ -401,6 +435,10 @@ KArgs base_args(const crkdg_mesh* m, const Group& g, crkdg_ctl* ctl) {
   a.n_items = g.nblocks;
   a.tile_shift = TILE_SHIFT;
   a.ctl = ctl;
+  a.src = m->src;
+  // stage times c_j = a_{j,j-1} (c_1 = 0): the tables are subdiagonal
+  const Butcher bt = butcher(g.stages);
+  for (int j = 1; j < 4; ++j) a.c[j] = (j < g.stages) ? bt.a[j + 1] : 0.0;
   return a;
 }
 
@@ -707,6 +745,7 @@ int crkdg_free_mesh(crkdg_mesh* m) {
   if (m->d_partial) hipFree(m->d_partial);
   if (m->d_queue) hipFree(m->d_queue);
   if (m->d_qcount) hipFree(m->d_qcount);
+  if (m->d_srcw) hipFree(m->d_srcw);
   delete m;
   return CRKDG_OK;
 }
@@ -788,6 +827,36 @@ int crkdg_project(crkdg_mesh* m, const double* d_samples, crkdg_state out, void*
     g.ops->project(a, g.nblocks, BLOCK, s);
   }
   HIP_TRY(hipGetLastError());
+  return CRKDG_OK;
+}
+
+int crkdg_set_source(crkdg_mesh* m, int32_t n_terms, const crkdg_state* terms, const double* coef) {
+  if (check_mesh(m)) return CRKDG_E_ARG;
+  if (n_terms < 0 || n_terms > CRKDG_MAX_SOURCE_TERMS)
+    return fail(CRKDG_E_ARG, "n_terms must lie in 0.." + std::to_string(CRKDG_MAX_SOURCE_TERMS));
+  if (n_terms > 0 && (!terms || !coef)) return fail(CRKDG_E_ARG, "NULL terms or coef");
+  if (m->live_graphs > 0)
+    return fail(CRKDG_E_ARG, "step graphs of this mesh are alive: they hold the previous source");
+  Src src{};
+  for (int p = 0; p < n_terms; ++p) {
+    if (int rc = check_state(terms[p], "terms[p]")) return rc;
+    for (int j = 0; j < 3; ++j)
+      if (!std::isfinite(coef[3 * p + j])) return fail(CRKDG_E_ARG, "non-finite source coefficient");
+    src.avg[p] = terms[p].avg;
+    src.hi[p] = terms[p].hi;
+    src.rate[p] = coef[3 * p];
+    src.omega[p] = coef[3 * p + 1];
+    src.phase[p] = coef[3 * p + 2];
+  }
+  src.n = n_terms;
+  if (n_terms > 0 && !m->d_srcw) {
+    if (int rc = set_device(m)) return rc;
+    const size_t bytes = sizeof(double) * static_cast<size_t>(m->layout.n_inst) * SRC_STAGES * MAX_SRC;
+    HIP_TRY(hipMalloc(&m->d_srcw, bytes));
+    HIP_TRY(hipMemset(m->d_srcw, 0, bytes));
+  }
+  src.w = m->d_srcw;
+  m->src = src;
   return CRKDG_OK;
 }
 
@@ -927,6 +996,17 @@ static int launch_stage(crkdg_mesh* m, int gi, int stage, const Slots& slots, cr
   const int qblocks = static_cast<int>(std::min<int64_t>(256, (g.ncells + BLOCK - 1) / BLOCK));
   const int grid = stage_grid(g);
   const bool persistent = grid < g.n_items;
+  if (m->src.n > 0) {
+    StageCoef sc{};
+    sc.a = (stage <= g.stages) ? bt.a[stage] : 0.0;
+    for (int j = 0; j < 4; ++j) {
+      sc.b[j] = bt.b[j];
+      sc.c[j] = a.c[j];
+    }
+    const int n = m->layout.n_inst;
+    hipLaunchKernelGGL(k_source_weights, dim3((n + 63) / 64), dim3(64), 0, s, m->d_inst, d_ctl, n, g.stages,
+                       stage, sc, m->src);
+  }
   if (g.ops->coop) {
     if (stage <= g.stages) {
       a.a = bt.a[stage];

@@ -205,6 +205,124 @@ def euler_wave(dim, n, k, space="Q", stages=None, seed=0, precision="fp64", amp=
     return Case(f"euler_wave_{dim}d", params, u0=lambda x: exact(x, 0.0), exact=exact)
 
 
+# ---------------------------------------------------------------------------
+# Manufactured solution of the 2D Euler accuracy test (Sec. 4.2, Example 4.2,
+# scenario I): rho = z sin(2 pi (x+y)) + 2, w = (z cos(2 pi x) sin(2 pi y) + 2,
+# z sin(2 pi x) cos(2 pi y) + 2), e = z cos(2 pi (x+y)) / 2 + 1 with
+# z = exp(-t), on [0,1]^2 (1-periodic in x and y), end time 0.1024.  Its
+# right-hand side s = dU/dt + div f(U) is problem data: it is formed here by
+# the chain rule from the closed-form primitives and their derivatives.
+# Every term of s is z^p times a function of x (p = 1..4: U is a polynomial
+# of degree <= 3 in z, the fluxes of degree <= 4, and dz/dt = -z), so
+# s(x, t) = sum_p exp(-p t) S_p(x) exactly.
+# ---------------------------------------------------------------------------
+MMS_T_END = 0.1024
+MMS_RATES = (1.0, 2.0, 3.0, 4.0)
+
+
+def _mms_fields(X, z, gamma=GAMMA):
+    """Primitives (rho, w1, w2, e) of scenario I at X[..., 2] with z = exp(-t)
+    (z may be complex), and their derivatives in t, x and y."""
+    x, y = X[..., 0], X[..., 1]
+    k = 2.0 * np.pi
+    S, C = np.sin(k * (x + y)), np.cos(k * (x + y))
+    sx, cx, sy, cy = np.sin(k * x), np.cos(k * x), np.sin(k * y), np.cos(k * y)
+    f = {
+        "rho": (z * S + 2.0, -z * S, k * z * C, k * z * C),
+        "w1": (z * cx * sy + 2.0, -z * cx * sy, -k * z * sx * sy, k * z * cx * cy),
+        "w2": (z * sx * cy + 2.0, -z * sx * cy, k * z * cx * cy, -k * z * sx * sy),
+        "e": (0.5 * z * C + 1.0, -0.5 * z * C, -0.5 * k * z * S, -0.5 * k * z * S),
+    }
+    return f
+
+
+def _mms_source_z(X, z, gamma=GAMMA):
+    """s = dU/dt + d f_1/dx + d f_2/dy of scenario I at X[..., 2], z = exp(-t)."""
+    f = _mms_fields(X, z, gamma)
+    r, rt, rx, ry = f["rho"]
+    u, ut, ux, uy = f["w1"]
+    v, vt, vx, vy = f["w2"]
+    e, et, ex, ey = f["e"]
+    g1 = gamma - 1.0
+    # pressure p = (gamma - 1) rho e and total energy E = rho e + rho |w|^2 / 2
+    p = g1 * r * e
+    px, py = g1 * (rx * e + r * ex), g1 * (ry * e + r * ey)
+    q = 0.5 * (u * u + v * v)
+    En = r * e + r * q
+    Et = rt * e + r * et + rt * q + r * (u * ut + v * vt)
+    Ex = rx * e + r * ex + rx * q + r * (u * ux + v * vx)
+    Ey = ry * e + r * ey + ry * q + r * (u * uy + v * vy)
+    mass = rt + (rx * u + r * ux) + (ry * v + r * vy)
+    mom1 = (rt * u + r * ut) + (rx * u * u + 2.0 * r * u * ux + px) + (ry * u * v + r * uy * v + r * u * vy)
+    mom2 = (rt * v + r * vt) + (rx * u * v + r * ux * v + r * u * vx) + (ry * v * v + 2.0 * r * v * vy + py)
+    ener = Et + ((Ex + px) * u + (En + p) * ux) + ((Ey + py) * v + (En + p) * vy)
+    return np.stack([mass, mom1, mom2, ener], axis=-1)
+
+
+def mms_euler2d_exact(X, t, gamma=GAMMA):
+    """Conservative (rho, m_1, m_2, E) of scenario I at X[..., 2] and time t."""
+    X = np.asarray(X, dtype=np.float64)
+    f = _mms_fields(X, math.exp(-t), gamma)
+    r, u, v, e = f["rho"][0], f["w1"][0], f["w2"][0], f["e"][0]
+    return np.stack([r, r * u, r * v, r * e + 0.5 * r * (u * u + v * v)], axis=-1)
+
+
+def mms_euler2d_source(X, t, gamma=GAMMA):
+    """The source s(x, t) of scenario I at X[..., 2] [..., 4]."""
+    return _mms_source_z(np.asarray(X, dtype=np.float64), math.exp(-t), gamma)
+
+
+def mms_euler2d_source_terms(X, gamma=GAMMA):
+    """The fields S_p(x), p = 1..4, of s(x, t) = sum_p exp(-p t) S_p(x):
+    the coefficients of the degree-4 polynomial z -> s(x, z), read off its
+    values at the fifth roots of unity (a discrete Fourier transform, exact
+    up to rounding).  Returns [4, ..., 4]; the z^0 coefficient is zero."""
+    X = np.asarray(X, dtype=np.float64)
+    zs = np.exp(2j * np.pi * np.arange(5) / 5.0)
+    vals = np.stack([_mms_source_z(X, z, gamma) for z in zs])          # [5, ..., 4]
+    coef = np.tensordot(np.exp(-2j * np.pi * np.outer(np.arange(5), np.arange(5)) / 5.0) / 5.0,
+                        vals, axes=(1, 0))
+    return np.ascontiguousarray(coef[1:].real)
+
+
+# step sizes and meshes of the accuracy table (Table 2): dt = 2^(5-l) 1e-5 on
+# the l-th mesh 1/2^(l + base[k])
+MMS_MESH_BASE = {1: 4, 2: 3, 3: 2}
+
+
+def mms_euler2d(k, level, space="P", precision="fp64", limiter=True):
+    """Example 4.2 scenario I on the level-th mesh of Table 2 (level 0..3)
+    for P^k / Q^k with the (k+1)-stage cRKDG scheme, fixed dt, periodic."""
+    n = 2 ** (MMS_MESH_BASE[k] + level)
+    dt = 2.0 ** (5 - level) * 1e-5
+    params = dict(dim=2, n=(n, n), system="euler", k=k, space=space, stages=k + 1, cfl=0.1,
+                  eps=1e-8, bc=("periodic", "periodic"), precision=precision, limiter=limiter)
+    return Case(f"mms_euler2d_{space}{k}_{n}", params, u0=lambda X: mms_euler2d_exact(X, 0.0),
+                t_end=MMS_T_END, exact=mms_euler2d_exact,
+                meta=dict(dt=dt, source=mms_euler2d_source, rates=MMS_RATES,
+                          source_terms=mms_euler2d_source_terms))
+
+
+def mms_advection_1d(k, n, precision="fp64", t_end=0.25, dt_per_dx=0.05):
+    """A manufactured solution of u_t + u_x = s on the periodic [0,1]:
+    u = exp(-t) sin(2 pi x) + 2, so s = exp(-t) (2 pi cos(2 pi x) - sin(2 pi x))
+    (one term of rate 1); P^k with k+1 stages, fixed dt = dt_per_dx dx."""
+    def exact(X, t):
+        return (math.exp(-t) * np.sin(2.0 * np.pi * np.asarray(X)[..., 0]) + 2.0)[..., None]
+
+    def term(X):
+        x = np.asarray(X, dtype=np.float64)[..., 0]
+        return (2.0 * np.pi * np.cos(2.0 * np.pi * x) - np.sin(2.0 * np.pi * x))[..., None]
+
+    def source(X, t):
+        return math.exp(-t) * term(X)
+
+    params = dict(dim=1, n=(n,), system="advection", k=k, stages=k + 1, cfl=0.1, vel=(1.0, 0.0, 0.0),
+                  bc=("periodic",), precision=precision, limiter=False)
+    return Case(f"mms_advection_1d_p{k}_{n}", params, u0=lambda X: exact(X, 0.0), t_end=t_end, exact=exact,
+                meta=dict(dt=dt_per_dx / n, source=source, rates=(1.0,), source_terms=lambda X: term(X)[None]))
+
+
 def batched_2d(seed=0, count=64, nmin=64, nmax=512, sites=16, precision="mixed"):
     rng = np.random.default_rng(seed)
     cases = []
