@@ -648,8 +648,11 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
 
   // r -= scale / dx_d * sum_b cface[f][b][m] * fn_b  for one face, fn = flux
   // through the face along +e_d (the sign of the outward normal is in cface).
+  // With H0, mode 0 takes the FP64 fluxes fn0[b] (scalar laws in the mixed
+  // form, see SPLIT0) instead of the FP32 ones.
+  template <bool H0 = false>
   __device__ __forceinline__ static void face_accum(int f, const T (&fn)[S::NFP][V], const InstDev& I,
-                                                    double scale, Acc& r) {
+                                                    double scale, Acc& r, const double* fn0 = nullptr) {
     const int d = f / 2;
     const double sc = scale * I.rdx[d];
     const T sct = T(sc);
@@ -663,7 +666,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
         // mode 0 in FP64, in the same order in both cells of the face
 #pragma unroll
         for (int b = 0; b < S::NFP; ++b)
-          r.a0[v] = cmad(-S::tab.cface[f][b][0], sc * static_cast<double>(fn[b][v]), r.a0[v]);
+          r.a0[v] = cmad(-S::tab.cface[f][b][0], sc * (H0 ? fn0[b] : static_cast<double>(fn[b][v])), r.a0[v]);
         T sum[(K + 2) / 2], dif[(K + 2) / 2];
 #pragma unroll
         for (int j = 0; j < (K + 2) / 2; ++j) {
@@ -704,7 +707,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
       for (int b = 0; b < S::NFP; ++b)
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-          r.a0[v] = cmad(-S::tab.cface[f][b][0], sc * static_cast<double>(fn[b][v]), r.a0[v]);
+          r.a0[v] = cmad(-S::tab.cface[f][b][0], sc * (H0 ? fn0[b] : static_cast<double>(fn[b][v])), r.a0[v]);
           const T g = sct * fn[b][v];
 #pragma unroll
           for (int m = 1; m < M; ++m) r.ah[v][m - 1] = cmad(-S::tab.cface[f][b][m], g, r.ah[v][m - 1]);
@@ -864,6 +867,23 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
     });
   }
 
+  // Mixed form of a scalar law: the fluxes that update the average (mode 0)
+  // are formed in FP64 from the traces ubar + delta_b, the FP64 average plus
+  // the FP32 trace of the higher modes, so that the average of a cell at a
+  // bound the data attain (the cells behind an inflow carrying the end of B)
+  // gets no FP32 rounding of ubar in its update; the higher modes keep the
+  // FP32 fluxes.  Both cells of a face form delta_b with the same operations
+  // (face_traces), so the FP64 face flux is still bitwise shared.
+  static constexpr bool SPLIT0 = (V == 1) && (sizeof(T) == 4);
+  __device__ __forceinline__ static void traces64(const State& s, int f, double (&u)[S::NFP]) {
+    State s0 = s;
+    s0.ub[0] = 0.0;
+    T dv[S::NFP][V];
+    face_traces(s0, f, dv);
+#pragma unroll
+    for (int b = 0; b < S::NFP; ++b) u[b] = s.ub[0] + static_cast<double>(dv[b][0]);
+  }
+
   // G = -div^loc f: interior trace flux on every face (Sec. 2.1).
   __device__ __forceinline__ static void op_local(const State& s, const InstDev& I, double scale,
                                                   Acc& r) {
@@ -882,7 +902,15 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
         const auto a = P::aux(tr[b], I);
         P::flux(tr[b], a, f / 2, I, fn[b]);
       }
-      face_accum(f, fn, I, scale, r);
+      if constexpr (SPLIT0) {
+        double u64[S::NFP], fn0[S::NFP];
+        traces64(s, f, u64);
+#pragma unroll
+        for (int b = 0; b < S::NFP; ++b) P::flux(&u64[b], P::aux(&u64[b], I), f / 2, I, &fn0[b]);
+        face_accum<true>(f, fn, I, scale, r, fn0);
+      } else {
+        face_accum(f, fn, I, scale, r);
+      }
     }
   }
 
@@ -955,8 +983,8 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
       const int64_t nb = neighbour(p, f, I);
       T ui[S::NFP][V], ue[S::NFP][V];
       face_traces(s, f, ui);
+      State sn;
       if (nb >= 0) {
-        State sn;
         getnb(f, nb, sn);
         face_traces(sn, f ^ 1, ue);
       } else if constexpr (WALLS) {
@@ -1005,7 +1033,45 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
             fn[b][v] = fma(-ha, uR[v] - uL[v], T(0.5) * (fL[b][v] + fR[b][v]));
         }
       }
-      face_accum(f, fn, I, scale, r);
+      if constexpr (SPLIT0) {
+        // the same Lax--Friedrichs flux in FP64 for the average update
+        double di[S::NFP], de[S::NFP], fn0[S::NFP];
+        traces64(s, f, di);
+        if (nb >= 0) {
+          traces64(sn, f ^ 1, de);
+        } else {
+#pragma unroll
+          for (int b = 0; b < S::NFP; ++b)
+            de[b] = (WALLS && I.bc[f] == CRKDG_BC_DIRICHLET) ? I.bcs[f][0] : di[b];
+        }
+        double a64 = 0.0;
+#pragma unroll
+        for (int b = 0; b < S::NFP; ++b) {
+          const double* uL = upper ? &di[b] : &de[b];
+          const double* uR = upper ? &de[b] : &di[b];
+          a64 = fmax(a64, fmax(P::speed(uL, P::aux(uL, I), d, I), P::speed(uR, P::aux(uR, I), d, I)));
+        }
+        if constexpr (ALPHA_MODES)
+          if (I.alpha_mode == CRKDG_ALPHA_GLOBAL) a64 = ag;
+        {
+#pragma clang fp contract(off)
+#pragma unroll
+          for (int b = 0; b < S::NFP; ++b) {
+            const double* uL = upper ? &di[b] : &de[b];
+            const double* uR = upper ? &de[b] : &di[b];
+            double ab = a64;
+            if (ALPHA_MODES && I.alpha_mode == CRKDG_ALPHA_POINT)
+              ab = fmin(fmax(P::speed(uL, P::aux(uL, I), d, I), P::speed(uR, P::aux(uR, I), d, I)), a64);
+            double fl, fr;
+            P::flux(uL, P::aux(uL, I), d, I, &fl);
+            P::flux(uR, P::aux(uR, I), d, I, &fr);
+            fn0[b] = fma(-0.5 * ab, *uR - *uL, 0.5 * (fl + fr));
+          }
+        }
+        face_accum<true>(f, fn, I, scale, r, fn0);
+      } else {
+        face_accum(f, fn, I, scale, r);
+      }
     }
   }
 

@@ -93,11 +93,10 @@ def test_heaviside_inflow_example(lib, k, precision):
     bound, 200 cells) to t = 0.5: the same accepted steps as the oracle
     (the average check's round-off margin keeps the cell at the inflow from
     being rejected), no violations, the inflow mass identity, the front at
-    x = 0.5."""
-    if (k, precision) == (3, "mixed"):
-        pytest.skip("mixed form with data on a bound: cells whose average sits at the bound get FP32-rounded "
-                    "mode-0 rates of ~2^-24/dx, so every attempt above dt ~ 1e-12 leaves B and is halved (the "
-                    "run stalls near t = 0.029); use the FP64 form for such data")
+    x = 0.5.  In the mixed form the average updates come from FP64 face
+    fluxes of FP64 averages plus FP32 trace deviations, so the cells at the
+    bound see no FP32 rounding of their averages and no attempt is halved,
+    as in FP64."""
     from test_oracle_boundaries import heaviside_problem
     p = heaviside_problem(k)
     params = dict(dim=1, n=p.n, system="advection", k=k, stages=p.stages, vel=(1.0, 0.0, 0.0), bc=("dirichlet",),
@@ -132,13 +131,7 @@ def test_heaviside_inflow_example(lib, k, precision):
     err = rel_err_per_var(C, o.to_legendre(U))
     _say(f"[heaviside P{k} {precision}] {c['accepted']} steps (oracle {n}), {c['rejected']} rejected, rel L1 to the "
          f"exact step {l1:.4f}, mass identity error {dm:.1e}, difference to the oracle {err:.1e}")
-    if precision == "fp64":
-        assert c["accepted"] == n and c["rejected"] == 0
-    else:
-        # the mixed form's face flux values are FP32: next to an inflow that
-        # carries the bound, an average can leave B by ~ dt/dx 2^-24 and the
-        # attempt is halved (measured: one halving in 654 steps)
-        assert c["rejected"] <= 3 and c["accepted"] <= n + c["rejected"]
+    assert c["accepted"] == n and c["rejected"] == 0
     assert o.bound_violations(o.from_legendre(C)) == 0
     assert abs(dm) < (1e-13 if precision == "fp64" else 1e-6)
     assert l1 < 0.005
