@@ -420,6 +420,11 @@ def summarise(name, r, args, mixed):
     return e
 
 
+def _progress(msg):
+    """A progress line on stderr (stdout carries only the result line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def workload(name, args, crkdg, inputs, torch, stream):
     """Mixed and FP64 runs of one workload (step throughput, final-stage
     roofline for single-instance meshes, mixed vs FP64 difference)."""
@@ -427,6 +432,7 @@ def workload(name, args, crkdg, inputs, torch, stream):
     finals = {}
     for prec in ("mixed",) + (() if args.no_fp64 else ("fp64",)):
         r, mesh, slots = measure(name, prec, args, crkdg, inputs, torch, stream, batched=(name == "batched"))
+        _progress(f"{name} {prec}: {r['ms'] / args.steps:.3f} ms per step")
         finals[prec] = (mesh, slots, r["cur"])
         out[prec] = summarise(name, r, args, prec == "mixed")
         out[prec]["_raw"] = r
@@ -457,6 +463,7 @@ def main():
     cpu = None
     if not args.no_cpu and not args.only and not args.copy_calibration:
         cpu = cpu_baseline(args.cpu_budget)
+        _progress(f"CPU baseline: {cpu['value']:.3e} {cpu['unit']} on {cpu['cores']} threads")
     import torch
 
     from paper_2412_16002_amd import crkdg, inputs
