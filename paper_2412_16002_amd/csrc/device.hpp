@@ -331,11 +331,12 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
   static constexpr int US = BIG ? 1 : NS;       // unroll of S_K loops
   static constexpr int TM = S::TM;
   using RT = Rt<D, K, SP, T>;
-  // Reflective and Dirichlet sides.  Not built into the 2D Q^3 Euler FP64
-  // kernels (64 FP64 values per state, spilling to scratch), whose final
-  // stage computed wrong values when the boundary code was added although it
-  // is never reached on periodic meshes; there only periodic and outflow
-  // sides are accepted.
+  // Reflective and Dirichlet sides.  Not built into one-thread-per-cell 2D
+  // Q^3 Euler FP64 stage kernels (64 FP64 values per state: 256 VGPRs, 256
+  // AGPRs and scratch), whose final stage computed wrong values with the
+  // boundary code in it although that code is never reached on periodic
+  // meshes.  That family now runs the cooperative stage kernels (coop.hpp),
+  // which have every boundary kind; these kernels are no longer built for it.
   static constexpr bool WALLS = BIG || MIXED || M * V <= 60;
   // The per-point and global Lax-Friedrichs alpha: not in the BIG face loop,
   // whose per-point pass runs at the register limit, nor in the 2D P^3 Euler

@@ -63,18 +63,15 @@ CASES = {
     "euler3d_q2_sides": dict(dim=3, n=(9, 6, 5), system="euler", k=2, stages=4, cfl=0.15,
                              bc=("reflect", "periodic", "dirichlet"), bc_upper=("reflect", "periodic", "outflow"),
                              bc_state={4: _cons(1.2, [0.0, 0.2, 0.4], 0.9)}),
-}
-FP64_TOL = 1e-12
-# mixed precision only: walls are not built into the FP64 2D Q^3 Euler kernels
-MIXED_ONLY = {
     "euler2d_q3_walls": dict(dim=2, n=(13, 11), system="euler", k=3, stages=4, cfl=0.09,
                              bc=("reflect", "dirichlet"), bc_upper=("outflow", "reflect"),
                              bc_state={2: _cons(0.7, [0.1, 0.2], 0.6)}),
 }
+FP64_TOL = 1e-12
 
 
 def _setup(lib, name, precision="fp64"):
-    params = dict({**CASES, **MIXED_ONLY}[name], precision=precision)
+    params = dict(CASES[name], precision=precision)
     return params, oracle.CRKDG(oracle_problem(params)), lib.Mesh(gpu_problem(params))
 
 
@@ -182,13 +179,3 @@ def test_inflow_mass_rate_on_gpu(lib):
             _say(f"[inflow {precision}] dt {info['dt']:.4e} mass gain {new - tot:.17g}")
             assert abs((new - tot) - info["dt"]) < 1e-14
             tot = new
-
-
-def test_walls_not_built_for_fp64_q3(lib):
-    """The 2D Q^3 Euler FP64 kernels carry no wall code: such a mesh is
-    refused with CRKDG_E_UNSUPPORTED; periodic and outflow sides work."""
-    params = dict(MIXED_ONLY["euler2d_q3_walls"], precision="fp64")
-    with pytest.raises(lib.CRKDGError) as e:
-        lib.Mesh(gpu_problem(params))
-    assert "not built" in str(e.value)
-    lib.Mesh(gpu_problem(dict(params, bc=("outflow", "periodic"), bc_upper=None, bc_state={})))
