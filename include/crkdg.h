@@ -76,6 +76,8 @@ extern "C" {
 #define CRKDG_SYS_ADVECTION 0 /* f(u) = a u, scalar */
 #define CRKDG_SYS_BURGERS 1   /* f_d(u) = u^2 / 2, scalar */
 #define CRKDG_SYS_EULER 2     /* compressible Euler, d + 2 variables */
+#define CRKDG_SYS_SHALLOW_WATER 3 /* shallow water (h, h w_1..h w_d), d + 1 variables, flat
+                                     bottom; the paper's Remark on other systems (Sec. 3.2) */
 
 #define CRKDG_SPACE_Q 0 /* degree <= k in each variable (1D: P^k) */
 #define CRKDG_SPACE_P 1 /* total degree <= k */
@@ -145,8 +147,11 @@ typedef struct crkdg_problem {
                           _REFLECT or _DIRICHLET (a periodic direction takes 0) */
   int32_t alpha;     /* CRKDG_ALPHA_* (0, per face, in a zeroed struct) */
   double bc_state[6][5]; /* Dirichlet state of side 2 d + (upper side), conservative
-                            variables (rho, m_1..m_dim, E; scalars use [0]); it must lie
-                            in the admissible set (B, or B^eps for Euler) */
+                            variables (rho, m_1..m_dim, E; shallow water h, h w_1..h w_dim;
+                            scalars use [0]); it must lie in the admissible set (B, or
+                            B^eps for Euler and shallow water) */
+  double gravity;    /* g of the shallow-water equations (> 0); their admissible set is
+                        h >= eps */
 } crkdg_problem;
 
 typedef struct crkdg_mesh crkdg_mesh; /* opaque handle */
@@ -227,7 +232,8 @@ const char *crkdg_last_error(void);
  * CRKDG_E_HIP.  Compiled, each in FP64 and mixed form: 1D P^1-P^3 (all
  * systems); 2D Q^1-Q^3 and P^1-P^3 (advection, Euler); 3D Q^1 and P^1
  * (advection, Euler), Q^2 and P^2 advection, Q^2 Euler; 3D P^2 Euler in the
- * mixed form only.  Burgers is 1D only. */
+ * mixed form only.  Burgers is 1D only.  Shallow water: 1D P^1-P^3 and 2D Q^1-Q^3, P^1-P^3,
+ * FP64 and mixed. */
 int crkdg_init_mesh(const crkdg_problem *problems, int32_t n_inst, crkdg_mesh **out,
                     crkdg_layout *layout);
 

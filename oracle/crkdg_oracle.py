@@ -71,6 +71,13 @@ design notes of the repository):
       both operators as its L2 projection (the volume Gauss rule) at the time
       of the stage value it is paired with: G(u, t) = -div^loc f(u) + P s(t),
       F likewise, with u~^(j) at t^n + c_j dt, c_j = sum_k a_jk.
+  A28 shallow-water equations (named by the paper as a system the method
+      extends to; the limiter it points to is that of positivity-preserving
+      DG for shallow water): the invariant region is h >= eps, and one factor
+      theta = (hbar - eps) / (hbar - min_{S_K} h), taken where the minimum is
+      below eps and clamped to [0, 1], scales every component (depth and
+      discharge alike, so the velocity of the limited polynomial stays that
+      of a convex combination); reflective walls mirror the normal discharge.
 """
 from __future__ import annotations
 
@@ -81,6 +88,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 ADVECTION, BURGERS, EULER = "advection", "burgers", "euler"
+SHALLOW_WATER = "shallow_water"
 PERIODIC, OUTFLOW, REFLECT, DIRICHLET = "periodic", "outflow", "reflect", "dirichlet"
 
 # Butcher tables of the three cRKDG schemes (Sec. 3.3): explicit midpoint
@@ -209,11 +217,14 @@ class Problem:
     max_halvings: int = 40
     limiter: bool = True
     alpha: str = "face"           # LF alpha per face (A1), per face point, or global
+    gravity: float = 1.0          # g of the shallow-water equations
     source: object = None         # s(X[..., d], t) -> [..., V]: right-hand side (A25)
 
     @property
     def nvars(self):
-        return self.dim + 2 if self.system == EULER else 1
+        if self.system == EULER:
+            return self.dim + 2
+        return self.dim + 1 if self.system == SHALLOW_WATER else 1
 
     def side_bc(self, dd, side):
         """Boundary kind of the lower (side < 0) or upper side of direction dd."""
@@ -254,8 +265,8 @@ class CRKDG:
             for j, kind in enumerate(kinds):
                 if kind not in (PERIODIC, OUTFLOW, REFLECT, DIRICHLET):
                     raise ValueError(f"unknown boundary kind {kind}")
-                if kind == REFLECT and prob.system != EULER:
-                    raise ValueError("reflective walls are defined for the Euler equations")
+                if kind == REFLECT and prob.system not in (EULER, SHALLOW_WATER):
+                    raise ValueError("reflective walls are defined for the Euler and shallow-water equations")
                 if kind == DIRICHLET and len(prob.bc_state.get(2 * dd + j, ())) != self.V:
                     raise ValueError("a Dirichlet side needs a state of V values")
 
@@ -424,6 +435,16 @@ class CRKDG:
             return p.vel[dd] * u
         if p.system == BURGERS:
             return 0.5 * u * u
+        if p.system == SHALLOW_WATER:
+            # (h w_dd, h w_j w_dd + g h^2 / 2 delta_j,dd)
+            h = u[..., 0]
+            mom = u[..., 1:1 + self.d]
+            w = mom[..., dd] / h
+            f = np.empty_like(u)
+            f[..., 0] = mom[..., dd]
+            for j in range(self.d):
+                f[..., 1 + j] = mom[..., j] * w + (0.5 * p.gravity * h * h if j == dd else 0.0)
+            return f
         rho = u[..., 0]
         mom = u[..., 1:1 + self.d]
         E = u[..., 1 + self.d]
@@ -443,6 +464,10 @@ class CRKDG:
             return np.full(u.shape[:-1], abs(p.vel[dd]))
         if p.system == BURGERS:
             return np.abs(u[..., 0])
+        if p.system == SHALLOW_WATER:
+            # |w_dd| + sqrt(g h); a negative depth (not admissible) counts as dry
+            h = u[..., 0]
+            return np.abs(u[..., 1 + dd] / h) + np.sqrt(p.gravity * np.fmax(h, 0.0))
         rho = u[..., 0]
         mom = u[..., 1:1 + self.d]
         E = u[..., 1 + self.d]
@@ -563,6 +588,8 @@ class CRKDG:
             with np.errstate(invalid="ignore", divide="ignore"):
                 ok &= avg[:, 0] >= p.eps
                 ok &= self.rho_e(avg) >= p.eps
+        elif p.system == SHALLOW_WATER:
+            ok &= avg[:, 0] >= p.eps
         else:
             tau = self.average_slack()
             ok &= (avg[:, 0] >= p.bound_lo - tau) & (avg[:, 0] <= p.bound_hi + tau)
@@ -587,6 +614,17 @@ class CRKDG:
         avg = self.cell_average(U)
         one = self.one[None, None, :]
         with np.errstate(invalid="ignore", divide="ignore"):
+            if p.system == SHALLOW_WATER:
+                # one factor from the depth, applied to every component (A28)
+                hs = np.einsum("cm,pm->cp", U[:, 0, :], self.phi_s)
+                hmin = hs.min(axis=1)
+                hb = avg[:, 0]
+                theta = np.ones(U.shape[0])
+                bad = hmin < p.eps
+                theta[bad] = (hb[bad] - p.eps) / (hb[bad] - hmin[bad])
+                theta = np.clip(np.where(np.isnan(theta), 0.0, theta), 0.0, 1.0)
+                out = theta[:, None, None] * (U - avg[:, :, None] * one) + avg[:, :, None] * one
+                return out, theta
             if p.system != EULER:
                 vals = np.einsum("cvm,pm->cvp", U, self.phi_s)[:, 0, :]
                 ub = avg[:, 0]
@@ -753,6 +791,10 @@ class CRKDG:
                 bad |= np.any(rho < p.eps - tr, axis=1)
                 bad |= np.any(q < p.eps * rho - tol_q, axis=1)
                 bad |= np.any((q <= 0.0) & (tol_q < p.eps * rho), axis=1)
+            elif p.system == SHALLOW_WATER:
+                h, th = us[..., 0], tol[:, None, 0]
+                bad |= np.any(h <= 0.0, axis=1)
+                bad |= np.any(h < p.eps - th, axis=1)
             else:
                 t = tol[:, None, 0] + self.average_slack()
                 bad |= np.any(us[..., 0] > p.bound_hi + t, axis=1)

@@ -18,7 +18,7 @@ import numpy as np
 _LIB_PATH = Path(__file__).resolve().parent / "_lib" / "libcrkdg.so"
 
 BC_PERIODIC, BC_OUTFLOW, BC_REFLECT, BC_DIRICHLET = 0, 1, 2, 3
-SYS_ADVECTION, SYS_BURGERS, SYS_EULER = 0, 1, 2
+SYS_ADVECTION, SYS_BURGERS, SYS_EULER, SYS_SHALLOW_WATER = 0, 1, 2, 3
 SPACE_Q, SPACE_P = 0, 1
 FP64, MIXED = 0, 1
 SCHEME_CRKDG, SCHEME_RKDG = 0, 1
@@ -37,7 +37,7 @@ class CProblem(C.Structure):
         ("k", C.c_int32), ("space", C.c_int32), ("stages", C.c_int32), ("precision", C.c_int32),
         ("limiter", C.c_int32), ("cfl", C.c_double), ("max_halvings", C.c_int32),
         ("scheme", C.c_int32), ("bc_upper", C.c_int32 * 3), ("alpha", C.c_int32),
-        ("bc_state", (C.c_double * 5) * 6),
+        ("bc_state", (C.c_double * 5) * 6), ("gravity", C.c_double),
     ]
 
 
@@ -166,6 +166,7 @@ class Problem:
     bc_upper: tuple = (0, 0, 0)   # upper side per direction; 0: as bc
     bc_state: dict = field(default_factory=dict)  # side 2 d + upper -> Dirichlet state
     alpha: int = ALPHA_FACE
+    gravity: float = 1.0
 
     def to_c(self) -> CProblem:
         p = CProblem()
@@ -180,6 +181,7 @@ class Problem:
         p.precision, p.limiter, p.max_halvings = self.precision, int(self.limiter), self.max_halvings
         p.gamma, p.bound_lo, p.bound_hi = self.gamma, self.bound_lo, self.bound_hi
         p.eps, p.cfl, p.scheme, p.alpha = self.eps, self.cfl, self.scheme, self.alpha
+        p.gravity = self.gravity
         for i in range(3):
             p.bc_upper[i] = int(self.bc_upper[i]) if i < len(self.bc_upper) else 0
         for side, vals in self.bc_state.items():
@@ -188,7 +190,8 @@ class Problem:
         return p
 
 
-_SYS_NAMES = {"advection": SYS_ADVECTION, "burgers": SYS_BURGERS, "euler": SYS_EULER}
+_SYS_NAMES = {"advection": SYS_ADVECTION, "burgers": SYS_BURGERS, "euler": SYS_EULER,
+              "shallow_water": SYS_SHALLOW_WATER}
 _BC_NAMES = {"periodic": BC_PERIODIC, "outflow": BC_OUTFLOW, "reflect": BC_REFLECT, "dirichlet": BC_DIRICHLET}
 _SCHEME_NAMES = {"crkdg": SCHEME_CRKDG, "rkdg": SCHEME_RKDG}
 
@@ -213,7 +216,8 @@ def problem_from_params(params: dict) -> Problem:
         scheme=_SCHEME_NAMES[params.get("scheme", "crkdg")],
         bc_upper=tuple(_BC_NAMES[b] for b in params["bc_upper"]) if params.get("bc_upper") else (0, 0, 0),
         bc_state=dict(params.get("bc_state", {})),
-        alpha={"face": ALPHA_FACE, "point": ALPHA_POINT, "global": ALPHA_GLOBAL}[params.get("alpha", "face")])
+        alpha={"face": ALPHA_FACE, "point": ALPHA_POINT, "global": ALPHA_GLOBAL}[params.get("alpha", "face")],
+        gravity=params.get("gravity", 1.0))
 
 
 class State:

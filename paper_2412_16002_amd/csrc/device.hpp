@@ -24,6 +24,7 @@ namespace crkdg {
 constexpr int SYS_ADV = CRKDG_SYS_ADVECTION;
 constexpr int SYS_BURG = CRKDG_SYS_BURGERS;
 constexpr int SYS_EULER = CRKDG_SYS_EULER;
+constexpr int SYS_SWE = CRKDG_SYS_SHALLOW_WATER;
 constexpr int BLOCK = 256;
 constexpr int MAX_SLOTS = 5;
 
@@ -47,6 +48,7 @@ struct InstDev {
   double gamma, blo, bhi, eps, cfl, vol;
   double blo_chk, bhi_chk;  // scalar average check: B widened by a round-off margin
   double bcs[6][5];  // Dirichlet states per side
+  double grav;       // g (shallow water)
 };
 
 // One work item = one tile of cells of one instance: blockDim.x consecutive
@@ -213,7 +215,7 @@ __device__ __forceinline__ void static_for(Fn&& fn) {
 // physics (Sec. 2.2.3 for Euler)
 // ---------------------------------------------------------------------------
 template <int D, int SYS> struct Phys {
-  static constexpr int V = (SYS == SYS_EULER) ? D + 2 : 1;
+  static constexpr int V = (SYS == SYS_EULER) ? D + 2 : (SYS == SYS_SWE) ? D + 1 : 1;
 
   // auxiliary quantities of one state shared by all directions
   template <typename T> struct Aux {
@@ -239,6 +241,12 @@ template <int D, int SYS> struct Phys {
         ke = fma(u[1 + j], a.w[j], ke);
       }
       a.p = T(I.gamma - 1.0) * (u[D + 1] - T(0.5) * ke);
+    } else if constexpr (SYS == SYS_SWE) {
+      // velocity and the hydrostatic term g h^2 / 2 (held in p)
+      a.ir = recip(u[0]);
+#pragma unroll
+      for (int j = 0; j < D; ++j) a.w[j] = u[1 + j] * a.ir;
+      a.p = T(0.5 * I.grav) * (u[0] * u[0]);
     }
     return a;
   }
@@ -251,6 +259,10 @@ template <int D, int SYS> struct Phys {
       f[0] = T(I.vel[d]) * u[0];
     } else if constexpr (SYS == SYS_BURG) {
       f[0] = T(0.5) * u[0] * u[0];
+    } else if constexpr (SYS == SYS_SWE) {
+      f[0] = u[1 + d];
+#pragma unroll
+      for (int j = 0; j < D; ++j) f[1 + j] = u[1 + j] * a.w[d] + (j == d ? a.p : T(0));
     } else {
       f[0] = u[1 + d];
 #pragma unroll
@@ -269,6 +281,9 @@ template <int D, int SYS> struct Phys {
       return T(fabs(I.vel[d]));
     } else if constexpr (SYS == SYS_BURG) {
       return fabs(u[0]);
+    } else if constexpr (SYS == SYS_SWE) {
+      // |w_d| + sqrt(g h); a negative depth (not admissible) counts as dry
+      return fabs(a.w[d]) + fsqrt(fmax(T(I.grav) * u[0], T(0)));
     } else {
       return fabs(a.w[d]) + fsqrt(fmax(T(I.gamma) * a.p * a.ir, T(0)));
     }
@@ -1112,6 +1127,8 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
       for (int j = 0; j < D; ++j) ke = fma(s.ub[1 + j], s.ub[1 + j], ke);
       const double rhoe = s.ub[D + 1] - 0.5 * ke / s.ub[0];
       return (s.ub[0] >= I.eps) && (rhoe >= I.eps);
+    } else if constexpr (SYS == SYS_SWE) {
+      return s.ub[0] >= I.eps;
     } else {
       return (s.ub[0] >= I.blo_chk) && (s.ub[0] <= I.bhi_chk);
     }
@@ -1147,6 +1164,8 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
         }
         const double E = sk_var(s, p, D + 1);
         ok = ok && (rho >= I.eps) && (fma(E, rho, -0.5 * ke) >= I.eps * rho);
+      } else if constexpr (SYS == SYS_SWE) {
+        ok = ok && (sk_var(s, p, 0) >= I.eps);
       } else {
         const double u = sk_var(s, p, 0);
         ok = ok && (u >= I.blo) && (u <= I.bhi);
@@ -1235,6 +1254,37 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
           check(u);
         }
       }
+    } else if constexpr (SYS == SYS_SWE) {
+      // depth >= eps with the rounding bound of the FP32 evaluation
+      T thr = T(I.eps) + T(2) * err[0];
+      if constexpr (MIXED) thr *= T(1 + 0x1p-20);
+      auto check = [&](const T* u) {
+        ok = ok && (u[0] >= thr);
+        if constexpr (A0) {
+          const auto ax = P::aux(u, I);
+#pragma unroll
+          for (int d = 0; d < D; ++d) am[d] = fmax(am[d], P::speed(u, ax, d, I));
+        }
+      };
+      if constexpr (SF) {
+        sk_points_sf(s, check);
+      } else {
+#pragma unroll US
+        for (int p = 0; p < NS; ++p) {
+          T u[V];
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            T a = ub[v];
+#pragma unroll
+            for (int m = 1; m < M; ++m) {
+              if constexpr (BIG) a = fma(RT::tab.phi_s[p][m], s.ch[v][m - 1], a);
+              else a = cmad(S::tab.phi_s[p][m], s.ch[v][m - 1], a);
+            }
+            u[v] = a;
+          }
+          check(u);
+        }
+      }
     } else {
       const double lo = I.blo, hi = I.bhi;
       auto check = [&](const T* pa) {
@@ -1298,6 +1348,8 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
       }
       const double qlo = fma(elo, rlo, -0.5 * mm);
       return qlo * (1.0 - 0x1p-40) >= I.eps * (s.ub[0] + R[0]);
+    } else if constexpr (SYS == SYS_SWE) {
+      return s.ub[0] - R[0] >= I.eps;
     } else {
       return (s.ub[0] - R[0] >= I.blo) && (s.ub[0] + R[0] <= I.bhi);
     }
@@ -1305,7 +1357,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
 
   // Scaling limiter on S_K, FP64 decisions.  Scalar: Prop. 2.4; Euler:
   // density step then internal-energy step on the density-limited polynomial
-  // (Sec. 2.2.3).  A factor only acts where its bound is violated; it is
+  // (Sec. 2.2.3); shallow water: one depth factor for every component.  A factor only acts where its bound is violated; it is
   // clamped to [0, 1].
   __device__ __forceinline__ static void limit_full(State& s, const InstDev& I) {
     double th_first = 1.0, th_rest = 1.0;
@@ -1358,6 +1410,18 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
       }
       th_first = th1 * th2;
       th_rest = th2;
+    } else if constexpr (SYS == SYS_SWE) {
+      // one depth factor scales every component (reading A28)
+      const double hb = s.ub[0];
+      double hmin = INFINITY;
+#pragma unroll US
+      for (int p = 0; p < NS; ++p) hmin = fmin(hmin, sk_var(s, p, 0));
+      double th = 1.0;
+      if (!(hmin >= I.eps)) {
+        th = (hb - I.eps) / (hb - hmin);
+        th = (th >= 0.0) ? fmin(th, 1.0) : 0.0;
+      }
+      th_first = th_rest = th;
     } else {
       const double ub = s.ub[0];
       double mx = -INFINITY, mn = INFINITY;

@@ -20,7 +20,7 @@ using namespace crkdg;
 namespace {
 
 using Registry = int (*)(const VariantOps**);
-const Registry kRegistries[] = {&variants_v1d, &variants_v2d_q_adv, &variants_v2d_p_adv, &variants_v2d_q12_euler, &variants_v2d_q3_euler, &variants_v2d_p_euler, &variants_v3d_q1, &variants_v3d_q2_adv, &variants_v3d_q2_euler, &variants_v3d_p, &variants_v3d_p2_euler};
+const Registry kRegistries[] = {&variants_v1d, &variants_v2d_q_adv, &variants_v2d_p_adv, &variants_v2d_q12_euler, &variants_v2d_q3_euler, &variants_v2d_p_euler, &variants_v3d_q1, &variants_v3d_q2_adv, &variants_v3d_q2_euler, &variants_v3d_p, &variants_v3d_p2_euler, &variants_swe_1d_q, &variants_swe_2d_p};
 
 thread_local std::string g_err = "";
 
@@ -204,11 +204,17 @@ int side_bc(const crkdg_problem& p, int d, int up) {
   return (up && p.bc_upper[d] != 0) ? p.bc_upper[d] : p.bc[d];
 }
 
-// a prescribed boundary state inside B (scalar) or B^eps (Euler)
+int n_vars_of(int system, int dim) {
+  if (system == CRKDG_SYS_EULER) return dim + 2;
+  return system == CRKDG_SYS_SHALLOW_WATER ? dim + 1 : 1;
+}
+
+// a prescribed boundary state inside B (scalar) or B^eps (Euler, shallow water)
 bool admissible_state(const crkdg_problem& p, const double* u) {
-  const int V = (p.system == CRKDG_SYS_EULER) ? p.dim + 2 : 1;
+  const int V = n_vars_of(p.system, p.dim);
   for (int v = 0; v < V; ++v)
     if (!std::isfinite(u[v])) return false;
+  if (p.system == CRKDG_SYS_SHALLOW_WATER) return u[0] >= p.eps;
   if (p.system != CRKDG_SYS_EULER) return u[0] >= p.bound_lo && u[0] <= p.bound_hi;
   double m2 = 0.0;
   for (int d = 0; d < p.dim; ++d) m2 += u[1 + d] * u[1 + d];
@@ -229,20 +235,23 @@ int validate(const crkdg_problem& p, int idx) {
       return bad("a periodic direction is periodic on both sides (bc_upper must be 0)");
     for (int up = 0; up < 2; ++up) {
       const int kind = side_bc(p, d, up);
-      if (kind == CRKDG_BC_REFLECT && p.system != CRKDG_SYS_EULER)
-        return bad("reflective walls are defined for the Euler equations");
+      if (kind == CRKDG_BC_REFLECT && p.system != CRKDG_SYS_EULER && p.system != CRKDG_SYS_SHALLOW_WATER)
+        return bad("reflective walls are defined for the Euler and shallow-water equations");
       if (kind == CRKDG_BC_DIRICHLET && !admissible_state(p, p.bc_state[2 * d + up]))
         return bad("Dirichlet state not finite or outside the admissible set");
     }
   }
-  if (p.system < 0 || p.system > 2) return bad("unknown system");
+  if (p.system < 0 || p.system > 3) return bad("unknown system");
   if (p.k < 1 || p.k > 3) return bad("k must be 1..3");
   if (p.space != CRKDG_SPACE_Q && p.space != CRKDG_SPACE_P) return bad("unknown space");
   if (p.stages < 2 || p.stages > 4) return bad("stages must be 2, 3 or 4");
   if (p.precision != CRKDG_FP64 && p.precision != CRKDG_MIXED) return bad("unknown precision");
   if (p.system == CRKDG_SYS_EULER && !(p.gamma > 1.0)) return bad("gamma must exceed 1");
-  if (p.system == CRKDG_SYS_EULER && !(p.eps > 0.0)) return bad("eps must be positive");
-  if (p.system != CRKDG_SYS_EULER && !(p.bound_lo <= p.bound_hi)) return bad("bound_lo > bound_hi");
+  if ((p.system == CRKDG_SYS_EULER || p.system == CRKDG_SYS_SHALLOW_WATER) && !(p.eps > 0.0))
+    return bad("eps must be positive");
+  if (p.system == CRKDG_SYS_SHALLOW_WATER && !(p.gravity > 0.0)) return bad("gravity must be positive");
+  if (p.system != CRKDG_SYS_EULER && p.system != CRKDG_SYS_SHALLOW_WATER && !(p.bound_lo <= p.bound_hi))
+    return bad("bound_lo > bound_hi");
   if (!(p.cfl > 0.0)) return bad("cfl must be positive");
   if (p.max_halvings < 0) return bad("max_halvings must be >= 0");
   if (p.scheme != CRKDG_SCHEME_CRKDG && p.scheme != CRKDG_SCHEME_RKDG) return bad("unknown scheme");
@@ -504,7 +513,6 @@ int stage_grid(const Group& g) {
   return (g.tune.grid > 0) ? std::min(g.tune.grid, g.n_items) : g.n_items;
 }
 
-int n_vars_of(int system, int dim) { return system == CRKDG_SYS_EULER ? dim + 2 : 1; }
 
 int set_device(const crkdg_mesh* m) {
   HIP_TRY(hipSetDevice(m->device));
@@ -624,6 +632,7 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
     I.alpha_mode = p.alpha;
     I.max_halvings = p.max_halvings;
     I.gamma = p.gamma;
+    I.grav = p.gravity;
     I.blo = p.bound_lo;
     I.bhi = p.bound_hi;
     {

@@ -323,6 +323,100 @@ def mms_advection_1d(k, n, precision="fp64", t_end=0.25, dt_per_dx=0.05):
                 meta=dict(dt=dt_per_dx / n, source=source, rates=(1.0,), source_terms=lambda X: term(X)[None]))
 
 
+# ---------------------------------------------------------------------------
+# Shallow water (flat bottom): U = (h, h w_1, .., h w_d), g = gravity
+# ---------------------------------------------------------------------------
+def swe_conservative(h, w):
+    """(h, w[..., d]) -> (h, h w) stacked on the last axis."""
+    h = np.asarray(h, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    return np.concatenate([h[..., None], h[..., None] * w], axis=-1)
+
+
+def swe_dam_break_1d(n=200, k=2, h_left=2.0, h_right=1.0, gravity=1.0, precision="fp64", eps=1e-12,
+                     t_end=0.3):
+    """A dam break on [-1, 1], still water on both sides: h = h_left for
+    x < 0, h_right for x > 0, the end states held as Dirichlet data (the
+    waves stay inside until t_end)."""
+    x = cell_centres((n,), lo=(-1.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0))[:, 0]
+    h = np.where(x < 0.0, h_left, h_right)
+    params = dict(dim=1, n=(n,), system="shallow_water", k=k, stages=k + 1, lo=(-1.0, 0.0, 0.0),
+                  hi=(1.0, 1.0, 1.0), bc=("dirichlet",), bc_state={0: [h_left, 0.0], 1: [h_right, 0.0]},
+                  gravity=gravity, eps=eps, cfl={1: 0.3, 2: 0.153, 3: 0.093}[k], precision=precision)
+    return Case(f"swe_dam_break_{n}", params, cell_states=swe_conservative(h, np.zeros((n, 1))), t_end=t_end,
+                meta=dict(h_left=h_left, h_right=h_right))
+
+
+def _swe_mms_fields(X, z):
+    """Primitives (h, w_1..w_d) of the manufactured shallow-water solution
+    and their derivatives [value, d/dt, d/dx_1, ..] with z = exp(-t):
+    h = z sin(2 pi sum x) + 3, w_j = z cos(2 pi x_j) + 1."""
+    d = X.shape[-1]
+    k = 2.0 * np.pi
+    sx = np.sum(X, axis=-1)
+    h = [z * np.sin(k * sx) + 3.0, -z * np.sin(k * sx)] + [k * z * np.cos(k * sx)] * d
+    ws = []
+    for j in range(d):
+        xj = X[..., j]
+        wj = [z * np.cos(k * xj) + 1.0, -z * np.cos(k * xj)]
+        wj += [(-k * z * np.sin(k * xj)) if i == j else 0.0 * xj for i in range(d)]
+        ws.append(wj)
+    return h, ws
+
+
+def _swe_mms_source_z(X, z, gravity):
+    """s = dU/dt + sum_i d f_i / dx_i of the manufactured solution."""
+    h, ws = _swe_mms_fields(X, z)
+    d = X.shape[-1]
+    out = []
+    # mass: h_t + sum_i (h w_i)_i
+    mass = h[1] + sum(h[2 + i] * ws[i][0] + h[0] * ws[i][2 + i] for i in range(d))
+    out.append(mass)
+    for j in range(d):
+        # (h w_j)_t + sum_i (h w_j w_i)_i + (g h^2 / 2)_j
+        m = h[1] * ws[j][0] + h[0] * ws[j][1]
+        for i in range(d):
+            m = m + (h[2 + i] * ws[j][0] * ws[i][0] + h[0] * ws[j][2 + i] * ws[i][0]
+                     + h[0] * ws[j][0] * ws[i][2 + i])
+        m = m + gravity * h[0] * h[2 + j]
+        out.append(m)
+    return np.stack(out, axis=-1)
+
+
+SWE_MMS_RATES = (1.0, 2.0, 3.0)
+
+
+def swe_mms_exact(X, t):
+    X = np.asarray(X, dtype=np.float64)
+    h, ws = _swe_mms_fields(X, math.exp(-t))
+    return swe_conservative(h[0], np.stack([w[0] for w in ws], axis=-1))
+
+
+def swe_mms_source(X, t, gravity=1.0):
+    return _swe_mms_source_z(np.asarray(X, dtype=np.float64), math.exp(-t), gravity)
+
+
+def swe_mms_source_terms(X, gravity=1.0):
+    """S_p, p = 1..3, of s = sum_p exp(-p t) S_p (s is a cubic in z = exp(-t)
+    with no constant term), read off at the fourth roots of unity."""
+    X = np.asarray(X, dtype=np.float64)
+    zs = np.exp(2j * np.pi * np.arange(4) / 4.0)
+    vals = np.stack([_swe_mms_source_z(X, z, gravity) for z in zs])
+    coef = np.tensordot(np.exp(-2j * np.pi * np.outer(np.arange(4), np.arange(4)) / 4.0) / 4.0, vals, axes=(1, 0))
+    return np.ascontiguousarray(coef[1:].real)
+
+
+def swe_mms(dim, n, k, space="Q", precision="fp64", t_end=0.1, dt_per_dx=0.01):
+    """The manufactured shallow-water solution on the periodic unit box, g = 1,
+    k+1 stages, fixed dt = dt_per_dx dx."""
+    params = dict(dim=dim, n=tuple([n] * dim), system="shallow_water", k=k, space=space, stages=k + 1,
+                  cfl=0.1, eps=1e-8, gravity=1.0, bc=("periodic",) * dim, precision=precision)
+    return Case(f"swe_mms_{dim}d_{space}{k}_{n}", params, u0=lambda X: swe_mms_exact(X, 0.0), t_end=t_end,
+                exact=swe_mms_exact,
+                meta=dict(dt=dt_per_dx / n, source=swe_mms_source, rates=SWE_MMS_RATES,
+                          source_terms=swe_mms_source_terms))
+
+
 def batched_2d(seed=0, count=64, nmin=64, nmax=512, sites=16, precision="mixed"):
     rng = np.random.default_rng(seed)
     cases = []

@@ -22,7 +22,8 @@ def oracle_problem(params: dict) -> oracle.Problem:
         eps=params.get("eps", 1e-8), cfl=params.get("cfl", 0.1),
         max_halvings=params.get("max_halvings", 40), limiter=bool(params.get("limiter", True)),
         bc_upper=tuple(params["bc_upper"]) if params.get("bc_upper") else None,
-        bc_state=dict(params.get("bc_state", {})), alpha=params.get("alpha", "face"))
+        bc_state=dict(params.get("bc_state", {})), alpha=params.get("alpha", "face"),
+        gravity=params.get("gravity", 1.0))
 
 
 def gpu_problem(params: dict):
@@ -40,6 +41,9 @@ def random_state(o: oracle.CRKDG, seed, rel_amp=0.05, limited=True, avg=None):
     if avg is None:
         if o.p.system == oracle.EULER:
             avg = inputs.random_euler_averages(o.ncell, o.d, seed=seed)
+        elif o.p.system == oracle.SHALLOW_WATER:
+            rng = np.random.default_rng(seed)
+            avg = inputs.swe_conservative(rng.uniform(0.5, 1.5, o.ncell), rng.uniform(-0.5, 0.5, (o.ncell, o.d)))
         else:
             lo, hi = o.p.bound_lo, o.p.bound_hi
             rng = np.random.default_rng(seed)
