@@ -303,6 +303,28 @@ def mms_euler2d(k, level, space="P", precision="fp64", limiter=True):
                           source_terms=mms_euler2d_source_terms))
 
 
+def mms_euler2d_scenario2_exact(X, t, gamma=GAMMA):
+    """Example 4.2 scenario II: rho = 0.99 sin(pi (x + y - 2 t)) + 1, w = (1, 1),
+    rho e = 1 / (gamma - 1) (p = 1): an exact solution (no source), density
+    down to 0.01."""
+    X = np.asarray(X, dtype=np.float64)
+    rho = 0.99 * np.sin(np.pi * (X[..., 0] + X[..., 1] - 2.0 * t)) + 1.0
+    return conservative(rho, np.ones(X.shape[:-1] + (2,)), np.ones(X.shape[:-1]), gamma)
+
+
+def mms_euler2d_scenario2(k, level, space="P", precision="fp64"):
+    """Scenario II on the meshes and steps of Table 3, on the periodic box
+    [0, 2]^2 (the solution has period 2 in x and y; the paper's [0, 1]^2 needs
+    time-dependent boundary data): the same mesh width 1/2^(level + base[k])
+    and dt = 2^(5-level) 1e-5, to t = 0.1024."""
+    n = 2 * 2 ** (MMS_MESH_BASE[k] + level)
+    dt = 2.0 ** (5 - level) * 1e-5
+    params = dict(dim=2, n=(n, n), system="euler", k=k, space=space, stages=k + 1, cfl=0.1, eps=1e-8,
+                  hi=(2.0, 2.0, 1.0), bc=("periodic", "periodic"), precision=precision)
+    return Case(f"mms_euler2d_s2_{space}{k}_{n}", params, u0=lambda X: mms_euler2d_scenario2_exact(X, 0.0),
+                t_end=MMS_T_END, exact=mms_euler2d_scenario2_exact, meta=dict(dt=dt))
+
+
 def mms_advection_1d(k, n, precision="fp64", t_end=0.25, dt_per_dx=0.05):
     """A manufactured solution of u_t + u_x = s on the periodic [0,1]:
     u = exp(-t) sin(2 pi x) + 2, so s = exp(-t) (2 pi cos(2 pi x) - sin(2 pi x))

@@ -219,3 +219,41 @@ def test_table2_convergence_on_gpu(lib, space, k):
          f"(printed finest {TABLE2_RATE[(space, k)]})")
     assert rates[-1] > k + 1 - 0.2
     assert abs(rates[-1] - TABLE2_RATE[(space, k)]) < 0.3
+
+
+# Table 3 (Example 4.2 scenario II, density down to 0.01): rates of the finest pair
+TABLE3_RATE = {("P", 1): 2.166, ("P", 2): 2.999, ("P", 3): 3.844,
+               ("Q", 1): 1.997, ("Q", 2): 2.953, ("Q", 3): 4.200}
+
+
+@pytest.mark.parametrize("space,k", sorted(TABLE3_RATE))
+def test_table3_convergence_on_gpu(lib, space, k):
+    """Scenario II (an exact Euler solution, no source) with the meshes and
+    steps of Table 3, on the periodic [0, 2]^2 (its period; the paper's
+    [0, 1]^2 needs time-dependent boundary data).  The errors are the L2
+    distance on [0, 2]^2, so only the rates compare with the printed ones."""
+    errs = []
+    for level in range(4):
+        cs = inputs.mms_euler2d_scenario2(k, level, space)
+        o = oracle.CRKDG(oracle_problem(cs.params))
+        mesh = lib.Mesh(gpu_problem(cs.params))
+        slots = mesh.new_slots()
+        u0 = _project_on_gpu(mesh, o, cs.u0)
+        mesh.limit(u0)
+        slots[0].copy_(u0)
+        ctl = mesh.new_ctl()
+        mesh.start(slots, ctl, t0=0.0, t_end=cs.t_end, dt_fixed=cs.meta["dt"])
+        steps = int(math.ceil(cs.t_end / cs.meta["dt"]))
+        for _ in range(steps + 2):
+            mesh.step(slots, ctl, sync=False)
+        torch.cuda.synchronize()
+        rec = mesh.ctl_read(ctl)[0]
+        assert rec["status"] == 4 and rec["rejected"] == 0, rec
+        got = o.from_legendre(mesh.get_legendre(slots[rec["cur"]]))
+        errs.append(_l2_error(o, got, cs.exact, rec["t"]))
+        _say(f"[table 3] {space}{k} N={o.n[0]} L2 error {errs[-1]:.4e}")
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(3)]
+    _say(f"[table 3] {space}{k} rates {', '.join(f'{r:.3f}' for r in rates)} "
+         f"(printed finest {TABLE3_RATE[(space, k)]})")
+    assert rates[-1] > k + 1 - 0.2
+    assert abs(rates[-1] - TABLE3_RATE[(space, k)]) < 0.3
