@@ -222,6 +222,13 @@ def measure(name, precision, args, crkdg, inputs, torch, stream, kernels=True, b
     if tuning is not None:
         r["tuning"] = [{k: t[k] for k in ("dim", "k", "stages", "n_inst", "n_cells", "threads", "tile_x",
                                           "grid", "ms")} for t in tuning]
+        # per kernel group: its stage kernels' pass (the tuner's time of the
+        # chosen shape) against the HBM roofline of the group's step bytes
+        for t in r["tuning"]:
+            L = next(L for L, p in zip(mesh.inst, mesh.problems) if p.k == t["k"] and p.dim == t["dim"]
+                     and L["n_stages"] == t["stages"])
+            gb = STEP_STATES[t["stages"]] * state_bytes(L["n_vars"], L["n_modes"], mixed) * t["n_cells"]
+            t["hbm_fraction"] = gb / (t["ms"] / 1e3) / 1e9 / HBM_PEAK_GBS
     if kernels and len(mesh.inst) == 1:
         r["kern"] = time_kernels(mesh, slots, ctl, args.kernel_reps, torch, stream)
         L = mesh.inst[0]

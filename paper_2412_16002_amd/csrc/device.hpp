@@ -49,6 +49,8 @@ struct InstDev {
   double blo_chk, bhi_chk;  // scalar average check: B widened by a round-off margin
   double bcs[6][5];  // Dirichlet states per side
   double grav;       // g (shallow water)
+  int32_t group;     // kernel group of the instance
+  int32_t pad2;
 };
 
 // One work item = one tile of cells of one instance: blockDim.x consecutive

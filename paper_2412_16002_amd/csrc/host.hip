@@ -126,6 +126,11 @@ struct crkdg_mesh {
   int live_graphs = 0;          // step graphs holding this mesh's stage maps
   Src src{};                    // source term (crkdg_set_source)
   double* d_srcw = nullptr;     // its per-stage weights [instance][SRC_STAGES][MAX_SRC]
+  // with several kernel groups, one stream per group so that their stage
+  // chains of an attempt overlap (fork and join through events)
+  std::vector<hipStream_t> gstreams;
+  std::vector<hipEvent_t> gjoin;
+  hipEvent_t gfork = nullptr;
 };
 
 namespace {
@@ -278,10 +283,10 @@ struct StageCoef {
   double b[4];
   double c[4];   // stage times c_1..c_s
 };
-__global__ void k_source_weights(const InstDev* inst, const crkdg_ctl* ctl, int n, int stages, int stage,
-                                 StageCoef sc, Src src) {
+__global__ void k_source_weights(const InstDev* inst, const crkdg_ctl* ctl, int n, int group, int stages,
+                                 int stage, StageCoef sc, Src src) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || inst[i].stages != stages || instance_idle(ctl + i)) return;
+  if (i >= n || inst[i].group != group || instance_idle(ctl + i)) return;
   const double t = ctl[i].t, dt = ctl[i].dt;
   double* w = src.w + (static_cast<int64_t>(i) * SRC_STAGES + stage) * MAX_SRC;
   for (int p = 0; p < src.n; ++p) {
@@ -666,6 +671,7 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
     }
     m->groups[g].insts.push_back(i);
     m->groups[g].dim = p.dim;
+    I.group = g;
     // the smallest tiles any tuning may use (64 threads) must stay countable
     const int64_t nb = instance_tile_count(p, BLOCK, TILE_X);
     if (nb + lblock > (int64_t(1) << 30) || instance_tile_count(p, 64, 8) > (int64_t(1) << 30)) {
@@ -730,6 +736,21 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
   const int nq = static_cast<int>(m->groups.size()) * QSTAGES;
   if ((e = hipMalloc(&m->d_qcount, sizeof(unsigned) * nq)) != hipSuccess) return cleanup("hipMalloc", e);
   if ((e = hipMemset(m->d_qcount, 0, sizeof(unsigned) * nq)) != hipSuccess) return cleanup("hipMemset", e);
+  if (m->groups.size() > 1) {
+    // streams (default priority) and events for the overlapped group chains
+    if ((e = hipEventCreateWithFlags(&m->gfork, hipEventDisableTiming)) != hipSuccess)
+      return cleanup("hipEventCreateWithFlags", e);
+    for (size_t gi = 0; gi < m->groups.size(); ++gi) {
+      hipStream_t st = nullptr;
+      hipEvent_t ev = nullptr;
+      if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess)
+        return cleanup("hipStreamCreateWithFlags", e);
+      m->gstreams.push_back(st);
+      if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+        return cleanup("hipEventCreateWithFlags", e);
+      m->gjoin.push_back(ev);
+    }
+  }
 
   crkdg_layout& lo = m->layout;
   lo.n_inst = n_inst;
@@ -755,6 +776,9 @@ int crkdg_free_mesh(crkdg_mesh* m) {
   if (m->d_queue) hipFree(m->d_queue);
   if (m->d_qcount) hipFree(m->d_qcount);
   if (m->d_srcw) hipFree(m->d_srcw);
+  for (hipStream_t st : m->gstreams) hipStreamDestroy(st);
+  for (hipEvent_t ev : m->gjoin) hipEventDestroy(ev);
+  if (m->gfork) hipEventDestroy(m->gfork);
   delete m;
   return CRKDG_OK;
 }
@@ -1013,8 +1037,8 @@ static int launch_stage(crkdg_mesh* m, int gi, int stage, const Slots& slots, cr
       sc.c[j] = a.c[j];
     }
     const int n = m->layout.n_inst;
-    hipLaunchKernelGGL(k_source_weights, dim3((n + 63) / 64), dim3(64), 0, s, m->d_inst, d_ctl, n, g.stages,
-                       stage, sc, m->src);
+    hipLaunchKernelGGL(k_source_weights, dim3((n + 63) / 64), dim3(64), 0, s, m->d_inst, d_ctl, n, gi,
+                       g.stages, stage, sc, m->src);
   }
   if (g.ops->coop) {
     if (stage <= g.stages) {
@@ -1080,11 +1104,26 @@ int crkdg_stage(crkdg_mesh* m, int32_t stage, const crkdg_state* states, int32_t
   return CRKDG_OK;
 }
 
+// One attempt of every running instance: the stage chain of each kernel
+// group, then the controller.  The groups touch disjoint instances, queue
+// regions and counters, so with several groups each chain runs on its own
+// stream (forked from s and joined back through events; under stream
+// capture this records parallel branches of the step graph): a group's
+// small or tail-heavy launches overlap the others'.
 static int enqueue_attempt(crkdg_mesh* m, const Slots& sl, crkdg_ctl* d_ctl, hipStream_t s) {
-  for (int stage = 2; stage <= m->max_stages + 1; ++stage)
-    for (int gi = 0; gi < static_cast<int>(m->groups.size()); ++gi)
-      if (stage <= m->groups[gi].stages + 1)
-        if (int rc = launch_stage(m, gi, stage, sl, d_ctl, s)) return rc;
+  const int ng = static_cast<int>(m->groups.size());
+  const bool fork = ng > 1 && static_cast<int>(m->gstreams.size()) == ng;
+  if (fork) HIP_TRY(hipEventRecord(m->gfork, s));
+  for (int gi = 0; gi < ng; ++gi) {
+    hipStream_t gs = fork ? m->gstreams[gi] : s;
+    if (fork) HIP_TRY(hipStreamWaitEvent(gs, m->gfork, 0));
+    for (int stage = 2; stage <= m->groups[gi].stages + 1; ++stage)
+      if (int rc = launch_stage(m, gi, stage, sl, d_ctl, gs)) return rc;
+    if (fork) {
+      HIP_TRY(hipEventRecord(m->gjoin[gi], gs));
+      HIP_TRY(hipStreamWaitEvent(s, m->gjoin[gi], 0));
+    }
+  }
   const int n = m->layout.n_inst;
   const int nq = static_cast<int>(m->groups.size()) * QSTAGES;
   hipLaunchKernelGGL(k_controller, dim3((std::max(n, nq) + 63) / 64), dim3(64), 0, s, d_ctl, m->d_inst, n,
