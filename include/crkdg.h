@@ -277,6 +277,27 @@ int crkdg_project(crkdg_mesh *mesh, const double *d_samples, crkdg_state out, vo
 #define CRKDG_MAX_SOURCE_TERMS 4
 int crkdg_set_source(crkdg_mesh *mesh, int32_t n_terms, const crkdg_state *terms, const double *coef);
 
+/* Time-dependent Dirichlet data on side `side` (2 d + upper) of instance
+ * `inst`, e.g. the exact-solution boundary data of the accuracy tests
+ * (Sec. 4.2): the exterior state at face point b of boundary face c is
+ *   sum_{p < n_terms} exp(-rate_p t) cos(omega_p t + phase_p) values[p][c][b][v]
+ * with coef[3 p + 0..2] = (rate_p, omega_p, phase_p) (host array) and
+ * `values` a caller-owned DEVICE array of FP64 [n_terms][n_faces][n_fp][V]:
+ * boundary faces c in natural order of the other directions (lower
+ * direction fastest, n_faces their product), face points b the tensor
+ * (k+1)-point Gauss points of the other directions (lower direction
+ * fastest, ascending; the 1D nodes are the first coordinates of the first
+ * k+1 volume points of crkdg_points), n_fp = (k+1)^(dim-1).  t is the time
+ * of the stage value the operator F acts on, t^n + c_j dt (the inner stages
+ * of the cRKDG scheme use no boundary data).  The side must be Dirichlet;
+ * its bc_state still serves the admissibility check at mesh creation.  The
+ * mesh keeps the pointer; n_terms = 0 returns the side to its constant
+ * state.  Refused while step graphs of the mesh exist (CRKDG_E_ARG) and for
+ * the cooperative 3D Q^2 / 2D Q^3 Euler kernels (CRKDG_E_UNSUPPORTED).
+ * Synchronous. */
+int crkdg_set_boundary_data(crkdg_mesh *mesh, int32_t inst, int32_t side, int32_t n_terms, const double *coef,
+                            const double *values);
+
 /* Scaling limiter in place (Prop. 2.4 scalar; Sec. 2.2.3 Euler).  Cell
  * averages are unchanged.  Cells whose average is outside B / B^eps raise
  * CRKDG_F_AVERAGE in d_ctl[inst].flags (theta is then clamped to [0,1]).

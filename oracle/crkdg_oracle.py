@@ -78,6 +78,9 @@ design notes of the repository):
       below eps and clamped to [0, 1], scales every component (depth and
       discharge alike, so the velocity of the limited polynomial stays that
       of a convex combination); reflective walls mirror the normal discharge.
+  A29 boundary data that depend on time (the exact-solution boundary data of
+      the accuracy tests, Sec. 4.2) are taken at the face quadrature points
+      at the time of the stage value the operator acts on, t^n + c_j dt.
 """
 from __future__ import annotations
 
@@ -208,6 +211,7 @@ class Problem:
     bc: tuple = (PERIODIC, PERIODIC, PERIODIC)   # per direction (both sides)
     bc_upper: tuple = None        # per direction, upper side; None: as `bc`
     bc_state: dict = field(default_factory=dict)  # side 2 d + (upper) -> Dirichlet state [V]
+    bc_function: dict = field(default_factory=dict)  # side -> g(X[..., d], t) -> [..., V] (A29)
     vel: tuple = (1.0, 1.0, 1.0)  # advection velocity
     gamma: float = 1.4
     bound_lo: float = -math.inf   # scalar invariant region B = [m, M]
@@ -267,7 +271,8 @@ class CRKDG:
                     raise ValueError(f"unknown boundary kind {kind}")
                 if kind == REFLECT and prob.system not in (EULER, SHALLOW_WATER):
                     raise ValueError("reflective walls are defined for the Euler and shallow-water equations")
-                if kind == DIRICHLET and len(prob.bc_state.get(2 * dd + j, ())) != self.V:
+                if (kind == DIRICHLET and 2 * dd + j not in prob.bc_function
+                        and len(prob.bc_state.get(2 * dd + j, ())) != self.V):
                     raise ValueError("a Dirichlet side needs a state of V values")
 
         # (k+1)-point Gauss rule, tensor volume rule (weights sum to 2^d)
@@ -546,8 +551,9 @@ class CRKDG:
         return (0.5 * side * (self.flux(um, dd) + self.flux(up, dd))
                 - 0.5 * a[:, :, None] * (up - um))
 
-    def face_traces(self, U, cells, face):
-        """Interior and exterior traces on `face` of `cells` -> ([c,b,V], [c,b,V])."""
+    def face_traces(self, U, cells, face, t=0.0):
+        """Interior and exterior traces on `face` of `cells` -> ([c,b,V], [c,b,V]);
+        t is the time of the state U (for boundary data that depend on it)."""
         Uc = U[cells]
         um = np.einsum("cvm,bm->cbv", Uc, face["phi"])
         nb = self.neighbour(cells, face["dim"], face["side"])
@@ -558,19 +564,24 @@ class CRKDG:
             up[..., 1 + face["dim"]] *= -1.0
         elif kind == DIRICHLET:                             # prescribed state (A22)
             j = 2 * face["dim"] + (1 if face["side"] > 0 else 0)
-            up[...] = np.asarray(self.p.bc_state[j], dtype=np.float64)
+            if j in self.p.bc_function:                     # data g(x, t) at the face points (A29)
+                X = self.physical_points(face["pts"], cells)
+                up[...] = np.asarray(self.p.bc_function[j](X, t), dtype=np.float64)
+            else:
+                up[...] = np.asarray(self.p.bc_state[j], dtype=np.float64)
         inner = nb >= 0
         if np.any(inner):
             up[inner] = np.einsum("cvm,bm->cbv", U[nb[inner]], opp["phi"])
         return um, up
 
-    def F(self, U, cells=None, a_glob=None):
+    def F(self, U, cells=None, a_glob=None, t=0.0):
         """DG operator F = -div^DG f with the Lax--Friedrichs flux (Sec. 2.1);
-        a_glob is the alpha of every face when Problem.alpha is "global"."""
+        a_glob is the alpha of every face when Problem.alpha is "global"; t
+        is the time of U (boundary data that depend on time)."""
         cells = np.arange(self.ncell) if cells is None else np.asarray(cells)
         r = self._volume_residual(U[cells])
         for face in self.faces:
-            um, up = self.face_traces(U, cells, face)
+            um, up = self.face_traces(U, cells, face, t)
             r -= self._face_residual(face, self.lf_flux(um, up, face["dim"], face["side"], a_glob))
         return np.linalg.solve(self.mass, r.reshape(-1, self.M).T).T.reshape(r.shape)
 
@@ -688,26 +699,27 @@ class CRKDG:
         c = A.sum(axis=1)
         s = self.p.stages
         out = Un.copy()
-        F = self.F
-        if self.p.alpha == "global":                     # a0 of u~^n (A1 option)
-            ag = float(np.max(self.a0(Un)))
+        ag = float(np.max(self.a0(Un))) if self.p.alpha == "global" else None   # a0 of u~^n (A1 option)
 
-            def F(V):
-                return self.F(V, a_glob=ag)
+        def F(V, tj):
+            return self.F(V, a_glob=ag, t=tj)
+
+        def G(V, tj):
+            return self.G(V)
 
         def with_source(value, j):
             src = self.source_term(t + c[j - 1] * dt)
             return value if src is None else value + src
 
         if i <= s:
-            inner = self.G if op is None else (F if op == self.F else op)
+            inner = G if op is None else (F if op == self.F else (lambda V, tj: op(V)))
             for j in range(1, i):
                 if A[i - 1, j - 1] != 0.0:
-                    out = out + dt * A[i - 1, j - 1] * with_source(inner(tilde[j - 1]), j)
+                    out = out + dt * A[i - 1, j - 1] * with_source(inner(tilde[j - 1], t + c[j - 1] * dt), j)
         else:
             for j in range(1, s + 1):
                 if b[j - 1] != 0.0:
-                    out = out + dt * b[j - 1] * with_source(F(tilde[j - 1]), j)
+                    out = out + dt * b[j - 1] * with_source(F(tilde[j - 1], t + c[j - 1] * dt), j)
         return out
 
     def attempt(self, Un, dt, op=None, t=0.0):

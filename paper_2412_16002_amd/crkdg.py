@@ -93,6 +93,8 @@ def _load():
         "crkdg_project": (C.c_int, [C.c_void_p, C.c_void_p, CState, C.c_void_p]),
         "crkdg_limit": (C.c_int, [C.c_void_p, CState, C.c_void_p, C.c_void_p]),
         "crkdg_set_source": (C.c_int, [C.c_void_p, C.c_int32, P(CState), P(C.c_double)]),
+        "crkdg_set_boundary_data": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, P(C.c_double),
+                                              C.c_void_p]),
         "crkdg_cell_avg": (C.c_int, [C.c_void_p, CState, C.c_void_p, C.c_void_p, C.c_void_p]),
         "crkdg_cell_avg_noalloc": (C.c_int, [C.c_void_p, CState, C.c_void_p, C.c_void_p, C.c_void_p]),
         "crkdg_cfl": (C.c_int, [C.c_void_p, CState, C.c_void_p, C.c_void_p]),
@@ -120,7 +122,8 @@ def _load():
 
 LIB = _load()
 EXPORTED = ("crkdg_last_error", "crkdg_init_mesh", "crkdg_free_mesh", "crkdg_instance_query",
-            "crkdg_points", "crkdg_project", "crkdg_limit", "crkdg_set_source", "crkdg_cell_avg",
+            "crkdg_points", "crkdg_project", "crkdg_limit", "crkdg_set_source", "crkdg_set_boundary_data",
+            "crkdg_cell_avg",
             "crkdg_cell_avg_noalloc",
             "crkdg_cfl",
             "crkdg_start", "crkdg_stage", "crkdg_step", "crkdg_group_count", "crkdg_get_tuning",
@@ -380,6 +383,20 @@ class Mesh:
         cf = (C.c_double * max(3 * n, 1))(*flat)
         _check(LIB.crkdg_set_source(self.h, n, cs, cf), "crkdg_set_source")
         self._source_terms = list(terms)
+
+    def set_boundary_data(self, inst, side, coef, values):
+        """crkdg_set_boundary_data: `values` a device float64 tensor
+        [n_terms, n_faces, n_fp, V] (kept alive here), coef a list of (rate,
+        omega, phase) triples; empty lists return the side to its constant
+        state."""
+        n = len(coef)
+        flat = [float(x) for c in coef for x in c]
+        cf = (C.c_double * max(3 * n, 1))(*flat)
+        ptr = C.c_void_p(values.data_ptr()) if n else None
+        _check(LIB.crkdg_set_boundary_data(self.h, inst, side, n, cf, ptr), "crkdg_set_boundary_data")
+        if not hasattr(self, "_bdata"):
+            self._bdata = {}
+        self._bdata[(inst, side)] = values
 
     def limit(self, u: State, ctl=None):
         _check(LIB.crkdg_limit(self.h, u.c(), None if ctl is None else C.c_void_p(ctl.data_ptr()),

@@ -50,7 +50,7 @@ struct InstDev {
   double bcs[6][5];  // Dirichlet states per side
   double grav;       // g (shallow water)
   int32_t group;     // kernel group of the instance
-  int32_t pad2;
+  uint32_t bdyn;     // bit f: side f takes time-dependent Dirichlet data (BSide)
 };
 
 // One work item = one tile of cells of one instance: blockDim.x consecutive
@@ -113,6 +113,19 @@ struct Src {
   int32_t pad;
 };
 
+// Time-dependent Dirichlet data of one side of one instance: the exterior
+// state at face point b of boundary face c (tangential cell index, the lower
+// tangential direction fastest) is sum_p g_p(t) val[((p n_faces + c) NFP +
+// b) V + v], g_p(t) = exp(-coef[p][0] t) cos(coef[p][1] t + coef[p][2]),
+// taken at the time of the stage value the operator acts on.
+struct BSide {
+  const double* val;
+  int32_t n_terms;
+  int32_t n_faces;
+  double coef[CRKDG_MAX_SOURCE_TERMS][3];
+};
+constexpr int BW_STAGES = 4;   // stage values per step with boundary weights
+
 struct KArgs {
   const InstDev* inst;
   const BlockItem* bmap;
@@ -131,7 +144,21 @@ struct KArgs {
   int32_t tile_shift;  // log2 of the tile width (2D/3D)
   double c[4];         // stage times c_1..c_s of the Butcher table (fractions of dt)
   Src src;
+  const BSide* bside;  // [instance][6] time-dependent boundary data (sides with I.bdyn set)
+  const double* bw;    // [instance][6][BW_STAGES][MAX_SRC] their time factors per stage value
 };
+
+// the time-dependent boundary data of one instance for stage value j
+// (0-based), or none
+struct BData {
+  const BSide* side;   // [6], null when the mesh has no such data
+  const double* w;     // [6][BW_STAGES][MAX_SRC] offset to stage value j
+};
+__device__ __forceinline__ BData bdata(const KArgs& a, int inst, int j) {
+  if (!a.bside) return BData{nullptr, nullptr};
+  return BData{a.bside + static_cast<int64_t>(inst) * 6,
+               a.bw + static_cast<int64_t>(inst) * 6 * BW_STAGES * MAX_SRC + j * MAX_SRC};
+}
 
 // ---------------------------------------------------------------------------
 // small helpers
@@ -978,21 +1005,46 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
   }
 
   // `ag` is the global alpha (used when I.alpha_mode is CRKDG_ALPHA_GLOBAL).
+  // `bd` locates the time-dependent boundary data of the instance for the
+  // stage value the operator acts on (null: none).
   __device__ __forceinline__ static void op_dg(const State& s, const double* avg, const T* hi,
                                                const CellPos& p, const InstDev& I, double scale, Acc& r,
-                                               double ag) {
+                                               double ag, const BData& bd) {
     if constexpr (BIG) {
       op_dg_big(s, avg, hi, p, I, scale, r);
     } else {
-      op_dg_from(s, p, I, scale, r, ag,
+      op_dg_from(s, p, I, scale, r, ag, bd,
                  [&](int, int64_t nb, State& sn) { load(avg, hi, I.ncell, nb, sn); });
     }
+  }
+
+  // the time-dependent exterior state (FP64) of variable v at face point b
+  // of side f of the cell at p
+  __device__ __forceinline__ static double bvalue(int f, const CellPos& p, const InstDev& I, const BData& bd,
+                                                  int b, int v) {
+    const BSide& bs = bd.side[f];
+    const double* w = bd.w + f * (BW_STAGES * MAX_SRC);
+    const int d = f / 2;
+    const int64_t fc = (d == 0) ? p.y + static_cast<int64_t>(I.n[1]) * p.z
+                     : (d == 1) ? p.x + static_cast<int64_t>(I.n[0]) * p.z
+                                : p.x + static_cast<int64_t>(I.n[0]) * p.y;
+    double x = 0.0;
+    for (int q = 0; q < bs.n_terms; ++q)
+      x = fma(w[q], bs.val[((static_cast<int64_t>(q) * bs.n_faces + fc) * S::NFP + b) * V + v], x);
+    return x;
+  }
+  // exterior traces of side f from its time-dependent data
+  __device__ __forceinline__ static void boundary_data(int f, const CellPos& p, const InstDev& I,
+                                                       const BData& bd, T (&ue)[S::NFP][V]) {
+    for (int b = 0; b < S::NFP; ++b)
+      for (int v = 0; v < V; ++v) ue[b][v] = T(bvalue(f, p, I, bd, b, v));
   }
 
   // F with the neighbour states read by getnb(f, nb, state)
   template <class GetNb>
   __device__ __forceinline__ static void op_dg_from(const State& s, const CellPos& p, const InstDev& I,
-                                                    double scale, Acc& r, double ag, GetNb getnb) {
+                                                    double scale, Acc& r, double ag, const BData& bd,
+                                                    GetNb getnb) {
     volume(s, I, scale, r);
 #pragma unroll
     for (int f = 0; f < S::NF; ++f) {
@@ -1006,8 +1058,12 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
         getnb(f, nb, sn);
         face_traces(sn, f ^ 1, ue);
       } else if constexpr (WALLS) {
+        if (bd.side && (I.bdyn & (1u << f))) {
+          boundary_data(f, p, I, bd, ue);
+        } else {
 #pragma unroll
-        for (int b = 0; b < S::NFP; ++b) ghost(f, I, ui[b], ue[b]);
+          for (int b = 0; b < S::NFP; ++b) ghost(f, I, ui[b], ue[b]);
+        }
       } else {
 #pragma unroll
         for (int b = 0; b < S::NFP; ++b)
@@ -1060,7 +1116,8 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
         } else {
 #pragma unroll
           for (int b = 0; b < S::NFP; ++b)
-            de[b] = (WALLS && I.bc[f] == CRKDG_BC_DIRICHLET) ? I.bcs[f][0] : di[b];
+            de[b] = !(WALLS && I.bc[f] == CRKDG_BC_DIRICHLET) ? di[b]
+                    : (bd.side && (I.bdyn & (1u << f))) ? bvalue(f, p, I, bd, b, 0) : I.bcs[f][0];
         }
         double a64 = 0.0;
 #pragma unroll
@@ -1557,7 +1614,7 @@ __device__ __forceinline__ void stage_local_item(const KArgs& a, const BlockItem
     typename C::Acc r;
     C::zero(r);
     if constexpr (DG)
-      C::op_dg(u, in_avg, in_hi, pos, I, dt * a.a, r, C::global_alpha(ctl));
+      C::op_dg(u, in_avg, in_hi, pos, I, dt * a.a, r, C::global_alpha(ctl), bdata(a, bi.inst, a.stage - 2));
     else
       C::op_local(u, I, dt * a.a, r);
     typename C::State base, out;
@@ -1636,7 +1693,7 @@ __device__ __forceinline__ void stage_final_item(const KArgs& a, const BlockItem
       const T* j_hi = hi_ptr<T>(sel_hi(a.slots, sl), I.hi_off);
       typename C::State uj;
       C::load(j_avg, j_hi, I.ncell, c, uj);
-      C::op_dg(uj, j_avg, j_hi, pos, I, dt * a.b[j - 1], r, C::global_alpha(ctl));
+      C::op_dg(uj, j_avg, j_hi, pos, I, dt * a.b[j - 1], r, C::global_alpha(ctl), bdata(a, bi.inst, j - 1));
     }
     typename C::State base;
     C::load(b_avg, b_hi, I.ncell, c, base);

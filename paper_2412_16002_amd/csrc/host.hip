@@ -131,6 +131,11 @@ struct crkdg_mesh {
   std::vector<hipStream_t> gstreams;
   std::vector<hipEvent_t> gjoin;
   hipEvent_t gfork = nullptr;
+  // time-dependent Dirichlet data (crkdg_set_boundary_data)
+  std::vector<BSide> bsides;    // [instance][6]
+  BSide* d_bside = nullptr;
+  double* d_bw = nullptr;       // [instance][6][BW_STAGES][MAX_SRC] time factors
+  bool has_bdata = false;
 };
 
 namespace {
@@ -305,6 +310,23 @@ __global__ void k_source_weights(const InstDev* inst, const crkdg_ctl* ctl, int 
   }
 }
 
+// Time factors g_p(t^n + c_j dt), j = 0..s-1, of the time-dependent boundary
+// data of every instance of `group` (one thread per instance and side).
+__global__ void k_boundary_weights(const InstDev* inst, const crkdg_ctl* ctl, const BSide* bside, double* bw,
+                                   int n, int group, int stages, StageCoef sc) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = e / 6, f = e % 6;
+  if (i >= n || inst[i].group != group || !(inst[i].bdyn & (1u << f)) || instance_idle(ctl + i)) return;
+  const BSide& bs = bside[e];
+  const double t = ctl[i].t, dt = ctl[i].dt;
+  double* w = bw + static_cast<int64_t>(e) * BW_STAGES * MAX_SRC;
+  for (int j = 0; j < stages && j < BW_STAGES; ++j) {
+    const double tj = t + sc.c[j] * dt;
+    for (int p = 0; p < bs.n_terms; ++p)
+      w[j * MAX_SRC + p] = exp(-bs.coef[p][0] * tj) * cos(fma(bs.coef[p][1], tj, bs.coef[p][2]));
+  }
+}
+
 __global__ void k_controller(crkdg_ctl* ctl, const InstDev* inst, int n, unsigned* qcount, int nq) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   // every deferred-limiter queue of this attempt has been drained
@@ -450,6 +472,8 @@ KArgs base_args(const crkdg_mesh* m, const Group& g, crkdg_ctl* ctl) {
   a.tile_shift = TILE_SHIFT;
   a.ctl = ctl;
   a.src = m->src;
+  a.bside = m->has_bdata ? m->d_bside : nullptr;
+  a.bw = m->d_bw;
   // stage times c_j = a_{j,j-1} (c_1 = 0): the tables are subdiagonal
   const Butcher bt = butcher(g.stages);
   for (int j = 1; j < 4; ++j) a.c[j] = (j < g.stages) ? bt.a[j + 1] : 0.0;
@@ -776,6 +800,8 @@ int crkdg_free_mesh(crkdg_mesh* m) {
   if (m->d_queue) hipFree(m->d_queue);
   if (m->d_qcount) hipFree(m->d_qcount);
   if (m->d_srcw) hipFree(m->d_srcw);
+  if (m->d_bside) hipFree(m->d_bside);
+  if (m->d_bw) hipFree(m->d_bw);
   for (hipStream_t st : m->gstreams) hipStreamDestroy(st);
   for (hipEvent_t ev : m->gjoin) hipEventDestroy(ev);
   if (m->gfork) hipEventDestroy(m->gfork);
@@ -890,6 +916,51 @@ int crkdg_set_source(crkdg_mesh* m, int32_t n_terms, const crkdg_state* terms, c
   }
   src.w = m->d_srcw;
   m->src = src;
+  return CRKDG_OK;
+}
+
+int crkdg_set_boundary_data(crkdg_mesh* m, int32_t inst, int32_t side, int32_t n_terms, const double* coef,
+                            const double* d_values) {
+  if (check_mesh(m)) return CRKDG_E_ARG;
+  if (inst < 0 || inst >= m->layout.n_inst) return fail(CRKDG_E_ARG, "instance out of range");
+  const crkdg_problem& p = m->probs[inst];
+  if (side < 0 || side >= 2 * p.dim) return fail(CRKDG_E_ARG, "side out of range");
+  if (side_bc(p, side / 2, side % 2) != CRKDG_BC_DIRICHLET) return fail(CRKDG_E_ARG, "the side is not Dirichlet");
+  if (n_terms < 0 || n_terms > CRKDG_MAX_SOURCE_TERMS)
+    return fail(CRKDG_E_ARG, "n_terms must lie in 0.." + std::to_string(CRKDG_MAX_SOURCE_TERMS));
+  if (n_terms > 0 && (!coef || !d_values)) return fail(CRKDG_E_ARG, "NULL coef or values");
+  if (m->live_graphs > 0)
+    return fail(CRKDG_E_ARG, "step graphs of this mesh are alive: they hold the previous boundary data");
+  const Group& g = m->groups[m->inst[inst].group];
+  if (g.ops->coop) return fail(CRKDG_E_UNSUPPORTED, "time-dependent boundary data: not built for this variant");
+  for (int j = 0; j < 3 * n_terms; ++j)
+    if (!std::isfinite(coef[j])) return fail(CRKDG_E_ARG, "non-finite coefficient");
+  if (int rc = set_device(m)) return rc;
+  const int n = m->layout.n_inst;
+  if (m->bsides.empty()) m->bsides.assign(static_cast<size_t>(n) * 6, BSide{});
+  if (!m->d_bside) {
+    HIP_TRY(hipMalloc(&m->d_bside, sizeof(BSide) * n * 6));
+    const size_t wb = sizeof(double) * static_cast<size_t>(n) * 6 * BW_STAGES * MAX_SRC;
+    HIP_TRY(hipMalloc(&m->d_bw, wb));
+    HIP_TRY(hipMemset(m->d_bw, 0, wb));
+  }
+  BSide bs{};
+  int64_t nf = 1;
+  for (int d = 0; d < p.dim; ++d)
+    if (d != side / 2) nf *= p.n[d];
+  bs.val = n_terms > 0 ? d_values : nullptr;
+  bs.n_terms = n_terms;
+  bs.n_faces = static_cast<int32_t>(nf);
+  for (int q = 0; q < n_terms; ++q)
+    for (int j = 0; j < 3; ++j) bs.coef[q][j] = coef[3 * q + j];
+  m->bsides[static_cast<size_t>(inst) * 6 + side] = bs;
+  InstDev& I = m->inst[inst];
+  if (n_terms > 0) I.bdyn |= 1u << side;
+  else I.bdyn &= ~(1u << side);
+  HIP_TRY(hipMemcpy(m->d_bside, m->bsides.data(), sizeof(BSide) * n * 6, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(m->d_inst + inst, &I, sizeof(InstDev), hipMemcpyHostToDevice));
+  m->has_bdata = false;
+  for (const InstDev& J : m->inst) m->has_bdata = m->has_bdata || J.bdyn != 0;
   return CRKDG_OK;
 }
 
@@ -1029,6 +1100,14 @@ static int launch_stage(crkdg_mesh* m, int gi, int stage, const Slots& slots, cr
   const int qblocks = static_cast<int>(std::min<int64_t>(256, (g.ncells + BLOCK - 1) / BLOCK));
   const int grid = stage_grid(g);
   const bool persistent = grid < g.n_items;
+  if (m->has_bdata && (stage > g.stages || g.scheme == CRKDG_SCHEME_RKDG)) {
+    // the stage evaluates F: time factors of the boundary data
+    StageCoef sc{};
+    for (int j = 0; j < 4; ++j) sc.c[j] = a.c[j];
+    const int n = m->layout.n_inst;
+    hipLaunchKernelGGL(k_boundary_weights, dim3((6 * n + 63) / 64), dim3(64), 0, s, m->d_inst, d_ctl,
+                       m->d_bside, m->d_bw, n, gi, g.stages, sc);
+  }
   if (m->src.n > 0) {
     StageCoef sc{};
     sc.a = (stage <= g.stages) ? bt.a[stage] : 0.0;

@@ -325,6 +325,81 @@ def mms_euler2d_scenario2(k, level, space="P", precision="fp64"):
                 t_end=MMS_T_END, exact=mms_euler2d_scenario2_exact, meta=dict(dt=dt))
 
 
+def boundary_face_points(params, side):
+    """Physical coordinates [n_faces, n_fp, d] of the face Gauss points of
+    side `side` (2 d + upper) of a box mesh: faces in natural order of the
+    other directions, points the tensor (k+1)-point Gauss points of the
+    other directions (both lower direction fastest)."""
+    d = params["dim"]
+    n = tuple(params["n"])[:d]
+    lo = tuple(params.get("lo", (0.0, 0.0, 0.0)))[:d]
+    hi = tuple(params.get("hi", (1.0, 1.0, 1.0)))[:d]
+    dd, up = side // 2, side % 2
+    g, _ = np.polynomial.legendre.leggauss(params["k"] + 1)
+    others = [j for j in range(d) if j != dd]
+    dx = [(hi[j] - lo[j]) / n[j] for j in range(d)]
+    cells = np.array(list(np.ndindex(*[n[j] for j in others][::-1])))[:, ::-1] if others else np.zeros((1, 0), int)
+    pts = np.array(list(np.ndindex(*([len(g)] * len(others))[::-1])))[:, ::-1] if others else np.zeros((1, 0), int)
+    X = np.zeros((len(cells), len(pts), d))
+    X[..., dd] = hi[dd] if up else lo[dd]
+    for a, j in enumerate(others):
+        X[..., j] = lo[j] + (cells[:, None, a] + 0.5 + 0.5 * g[pts[None, :, a]]) * dx[j]
+    return X
+
+
+def boundary_values(params, side, terms):
+    """Boundary data values [n_terms, n_faces, n_fp, V] of time-separable
+    Dirichlet data sum_p g_p(t) G_p(x): terms = [G_p(X[..., d]) -> [..., V]]."""
+    X = boundary_face_points(params, side)
+    return np.ascontiguousarray(np.stack([np.asarray(G(X), dtype=np.float64) for G in terms]))
+
+
+# the exact data of scenario II as three time-separable terms: rho = 1 + 0.99
+# (sin(pi s) cos(2 pi t) - cos(pi s) sin(2 pi t)), s = x + y; U is affine in rho
+SCENARIO2_COEF = ((0.0, 0.0, 0.0), (0.0, 2.0 * math.pi, 0.0), (0.0, 2.0 * math.pi, -0.5 * math.pi))
+
+
+def scenario2_boundary_terms(gamma=GAMMA):
+    one = np.array([1.0, 1.0, 1.0, 1.0])
+    base = np.array([1.0, 1.0, 1.0, 1.0 / (gamma - 1.0) + 1.0])
+    return [lambda X: np.broadcast_to(base, X.shape[:-1] + (4,)),
+            lambda X: 0.99 * np.sin(np.pi * (X[..., 0] + X[..., 1]))[..., None] * one,
+            lambda X: -0.99 * np.cos(np.pi * (X[..., 0] + X[..., 1]))[..., None] * one]
+
+
+def mms_euler2d_scenario2_box(k, level, space="P", precision="fp64"):
+    """Scenario II on the paper's [0, 1]^2 with the exact solution as
+    Dirichlet data on all four sides (Table 3's meshes and steps)."""
+    n = 2 ** (MMS_MESH_BASE[k] + level)
+    dt = 2.0 ** (5 - level) * 1e-5
+    st = [float(v) for v in mms_euler2d_scenario2_exact(np.zeros((1, 2)), 0.0)[0]]
+    params = dict(dim=2, n=(n, n), system="euler", k=k, space=space, stages=k + 1, cfl=0.1, eps=1e-8,
+                  bc=("dirichlet", "dirichlet"), bc_state={f: st for f in range(4)}, precision=precision)
+    return Case(f"mms_euler2d_s2box_{space}{k}_{n}", params, u0=lambda X: mms_euler2d_scenario2_exact(X, 0.0),
+                t_end=MMS_T_END, exact=mms_euler2d_scenario2_exact,
+                meta=dict(dt=dt, bc_coef=SCENARIO2_COEF, bc_terms=scenario2_boundary_terms()))
+
+
+def table1_advection(k, level, precision="fp64"):
+    """Example 4.1: u_t + u_x = 0 on [0, 1], u = sin(2 pi (x - t)) + 2 in [1, 3],
+    the meshes and steps of Table 1 (dt = 2^(4-level) 1e-4, dx = 1/2^(level +
+    5 - k)... per k), t = 0.1024, the exact inflow u(0, t) = 2 - sin(2 pi t)
+    as Dirichlet data on the left, outflow on the right, limiter on B = [1, 3]."""
+    n = 2 ** ({1: 5, 2: 4, 3: 3}[k] + level)
+    dt = 2.0 ** (4 - level) * 1e-4
+
+    def exact(X, t):
+        return (np.sin(2.0 * np.pi * (np.asarray(X)[..., 0] - t)) + 2.0)[..., None]
+
+    params = dict(dim=1, n=(n,), system="advection", k=k, stages=k + 1, cfl=0.1, vel=(1.0, 0.0, 0.0),
+                  bc=("dirichlet",), bc_upper=("outflow",), bc_state={0: [2.0]}, bound_lo=1.0, bound_hi=3.0,
+                  precision=precision)
+    return Case(f"table1_p{k}_{n}", params, u0=lambda X: exact(X, 0.0), t_end=0.1024, exact=exact,
+                meta=dict(dt=dt, bc_coef=((0.0, 0.0, 0.0), (0.0, 2.0 * math.pi, -0.5 * math.pi)),
+                          bc_terms=[lambda X: np.full(X.shape[:-1] + (1,), 2.0),
+                                    lambda X: np.full(X.shape[:-1] + (1,), -1.0)]))
+
+
 def mms_advection_1d(k, n, precision="fp64", t_end=0.25, dt_per_dx=0.05):
     """A manufactured solution of u_t + u_x = s on the periodic [0,1]:
     u = exp(-t) sin(2 pi x) + 2, so s = exp(-t) (2 pi cos(2 pi x) - sin(2 pi x))
