@@ -175,6 +175,9 @@ typedef struct crkdg_instance_layout {
   int32_t pad;
   int64_t avg_offset; /* element offset of this instance in avg */
   int64_t hi_offset;  /* element offset of this instance in hi */
+  int64_t sample_offset; /* element offset of this instance's block in crkdg_project's samples:
+                            the blocks ([v][K][q], n_vars x n_cells x n_vol_pts elements) are
+                            packed in instance order */
 } crkdg_instance_layout;
 
 /* One state: device pointers to the two arrays described above. */
@@ -252,8 +255,8 @@ int crkdg_points(const crkdg_mesh *mesh, int32_t inst, int32_t which, double *xy
 
 /* Discrete L2 projection with the volume Gauss rule (the initial-data
  * projection): d_samples holds u at the volume Gauss points of every cell,
- * layout [v][K][q] per instance, instances packed with element offset
- * avg_offset * n_vol_pts.  Writes the modal state `out`.  The result is not
+ * layout [v][K][q] per instance, instance blocks packed one after another
+ * (element offset sample_offset of crkdg_instance_query).  Writes the modal state `out`.  The result is not
  * limited: call crkdg_limit afterwards (the bound-preservation theorem,
  * Thm. 3.5, assumes a limited u^0). */
 int crkdg_project(crkdg_mesh *mesh, const double *d_samples, crkdg_state out, void *stream);

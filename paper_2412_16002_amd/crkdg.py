@@ -49,7 +49,8 @@ class CLayout(C.Structure):
 class CInstLayout(C.Structure):
     _fields_ = [("n_cells", C.c_int64), ("n_modes", C.c_int32), ("n_vars", C.c_int32),
                 ("n_stages", C.c_int32), ("n_vol_pts", C.c_int32), ("n_sk_pts", C.c_int32),
-                ("pad", C.c_int32), ("avg_offset", C.c_int64), ("hi_offset", C.c_int64)]
+                ("pad", C.c_int32), ("avg_offset", C.c_int64), ("hi_offset", C.c_int64),
+                ("sample_offset", C.c_int64)]
 
 
 class CState(C.Structure):

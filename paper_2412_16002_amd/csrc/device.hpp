@@ -33,6 +33,7 @@ struct InstDev {
   int64_t ncell;
   int64_t avg_off;   // element offset inside a state's avg array
   int64_t hi_off;    // element offset inside a state's hi array
+  int64_t smp_off;   // element offset of the instance's point samples (crkdg_project)
   int32_t n[3];
   int32_t bc[6];     // CRKDG_BC_* per side 2 d + (upper side)
   int32_t stages;
@@ -1846,7 +1847,7 @@ __global__ __launch_bounds__(BLOCK) void k_project(KArgs a) {
   const InstDev& I = a.inst[bi.inst];
   double* avg = a.slots.avg[0] + I.avg_off;
   T* hi = hi_ptr<T>(a.slots.hi[0], I.hi_off);
-  const double* smp = a.samples + I.avg_off * S::NQ;
+  const double* smp = a.samples + I.smp_off;
   bool active;
   const int64_t c = tile_cell(bi, D, I.n, I.ncell, a.tile_shift, active);
   if (!active) return;

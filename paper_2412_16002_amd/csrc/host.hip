@@ -582,7 +582,7 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
     }
   }
   std::map<std::tuple<const VariantOps*, int, int>, int> gidx;
-  int64_t avg_off = 0, hi_off = 0;
+  int64_t avg_off = 0, hi_off = 0, smp_off = 0;
   m->inst.resize(n_inst);
   m->lay.resize(n_inst);
   std::vector<std::vector<BlockItem>> logical;
@@ -628,14 +628,17 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
     L.n_sk_pts = ops->NS;
     L.avg_offset = avg_off;
     L.hi_offset = hi_off;
+    L.sample_offset = smp_off;
     avg_off += static_cast<int64_t>(ops->V) * nc;
     hi_off += static_cast<int64_t>(ops->V) * (ops->M - 1) * nc;
+    smp_off += static_cast<int64_t>(ops->V) * ops->NQ * nc;
 
     InstDev& I = m->inst[i];
     std::memset(&I, 0, sizeof(I));
     I.ncell = nc;
     I.avg_off = L.avg_offset;
     I.hi_off = L.hi_offset;
+    I.smp_off = L.sample_offset;
     double vol = 1.0;
     for (int d = 0; d < 3; ++d) {
       if (d < p.dim) {
