@@ -1020,9 +1020,12 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
   }
 
   // the time-dependent exterior state (FP64) of variable v at face point b
-  // of side f of the cell at p
-  __device__ __forceinline__ static double bvalue(int f, const CellPos& p, const InstDev& I, const BData& bd,
-                                                  int b, int v) {
+  // of side f of the cell at p.  Not inlined: only boundary cells of sides
+  // with such data call it, and inlined its index arithmetic and term loop
+  // took the 2D Q^2 Euler final stage from 244 to 272 registers (one
+  // wavefront per SIMD instead of two) although periodic meshes never run it.
+  __device__ __attribute__((noinline)) static double bvalue(int f, const CellPos& p, const InstDev& I,
+                                                            const BData& bd, int b, int v) {
     const BSide& bs = bd.side[f];
     const double* w = bd.w + f * (BW_STAGES * MAX_SRC);
     const int d = f / 2;
