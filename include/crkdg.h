@@ -296,7 +296,7 @@ int crkdg_set_source(crkdg_mesh *mesh, int32_t n_terms, const crkdg_state *terms
  * its bc_state still serves the admissibility check at mesh creation.  The
  * mesh keeps the pointer; n_terms = 0 returns the side to its constant
  * state.  Refused while step graphs of the mesh exist (CRKDG_E_ARG) and for
- * the cooperative 3D Q^2 / 2D Q^3 Euler kernels (CRKDG_E_UNSUPPORTED).
+ * the cooperative 3D Q^2 Euler kernels (CRKDG_E_UNSUPPORTED).
  * Synchronous. */
 int crkdg_set_boundary_data(crkdg_mesh *mesh, int32_t inst, int32_t side, int32_t n_terms, const double *coef,
                             const double *values);

@@ -507,7 +507,8 @@ struct Coop {
   // slots; then the face residuals of both faces of the cell
   template <int d, bool DG>
   __device__ __forceinline__ static void faces(const Geo& g, const double* avg, const T* hi, const InstDev& I,
-                                               double scale, double ag, T (&r)[M], double& r0, Smem& sm) {
+                                               double scale, double ag, T (&r)[M], double& r0, Smem& sm,
+                                               const BData& bd) {
     constexpr int NFD = nfd(d);
     constexpr int T1 = tsz1(d), T2 = tsz2(d);
     const int q1 = g.l[oax1(d)];
@@ -574,7 +575,7 @@ struct Coop {
       for (int pass = 0; pass < PASSES; ++pass) {
         const int fi = (pass * V + g.v) * GPW + grp;
         T uL[V], uR[V];
-        const bool use = grp < GPW && fi < NFD && face_pair<d>(g, I, fi, b, uL, uR, sm);
+        const bool use = grp < GPW && fi < NFD && face_pair<d>(g, I, fi, b, uL, uR, sm, bd);
         if (!use)
 #pragma unroll
           for (int w = 0; w < V; ++w) uL[w] = uR[w] = T(1);
@@ -686,7 +687,7 @@ struct Coop {
   // ghosts on non-periodic mesh sides; false when the slot is not used
   template <int d>
   __device__ __forceinline__ static bool face_pair(const Geo& g, const InstDev& I, int fi, int b, T (&uL)[V],
-                                                   T (&uR)[V], Smem& sm) {
+                                                   T (&uR)[V], Smem& sm, const BData& bd) {
     constexpr int T1 = tsz1(d);
     const int p = fi % (tdim(d) + 1);
     const int qq = fi / (tdim(d) + 1);
@@ -703,6 +704,20 @@ struct Coop {
     }
     if (ghost_lo) ghost(2 * d, I, uR, uL);
     if (ghost_up) ghost(2 * d + 1, I, uL, uR);
+    if constexpr (D == 2) {
+      // time-dependent Dirichlet data (2D variants only; boundary face
+      // index along the tangential direction)
+      const int f = ghost_lo ? 2 * d : 2 * d + 1;
+      if (bd.side && (ghost_lo || ghost_up) && (I.bdyn & (1u << f))) {
+        const int64_t fc = g.o[oax1(d)] + q1;
+#pragma unroll
+        for (int w = 0; w < V; ++w) {
+          const T x = T(boundary_value(bd, f, fc, NFP, V, b, w));
+          if (ghost_lo) uL[w] = x;
+          else uR[w] = x;
+        }
+      }
+    }
     return true;
   }
 
@@ -723,11 +738,12 @@ struct Coop {
   // accumulated into r, r0 with `scale`
   template <bool DG>
   __device__ __forceinline__ static void op(const Geo& g, const double* avg, const T* hi, const InstDev& I,
-                                            double scale, double ag, T (&r)[M], double& r0, Smem& sm) {
+                                            double scale, double ag, T (&r)[M], double& r0, Smem& sm,
+                                            const BData& bd) {
     volume(g, avg, hi, I, scale, r, sm);
-    faces<0, DG>(g, avg, hi, I, scale, ag, r, r0, sm);
-    faces<1, DG>(g, avg, hi, I, scale, ag, r, r0, sm);
-    if constexpr (D == 3) faces<2, DG>(g, avg, hi, I, scale, ag, r, r0, sm);
+    faces<0, DG>(g, avg, hi, I, scale, ag, r, r0, sm, bd);
+    faces<1, DG>(g, avg, hi, I, scale, ag, r, r0, sm, bd);
+    if constexpr (D == 3) faces<2, DG>(g, avg, hi, I, scale, ag, r, r0, sm, bd);
   }
 
   // ---- S_K values of one family (Lobatto nodes along fam, Gauss nodes
@@ -826,14 +842,16 @@ struct Coop {
         int tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
         const Geo gj = geo(bi, I, tid);
-        op<true>(gj, j_avg, j_hi, I, dt * a.b[j - 1], ag, r, r0, sm);
+        op<true>(gj, j_avg, j_hi, I, dt * a.b[j - 1], ag, r, r0, sm,
+                 D == 2 ? bdata(a, bi.inst, j - 1) : BData{nullptr, nullptr});
       });
     } else {
       const int sl_in = (cur + a.stage - 2) % nsl;
       sl_out = (cur + a.stage - 1) % nsl;
       const double* in_avg = sel_avg(a.slots, sl_in) + I.avg_off;
       const T* in_hi = hi_ptr<T>(sel_hi(a.slots, sl_in), I.hi_off);
-      op<KIND == 1>(g, in_avg, in_hi, I, dt * a.a, ag, r, r0, sm);
+      op<KIND == 1>(g, in_avg, in_hi, I, dt * a.a, ag, r, r0, sm,
+                    (D == 2 && KIND == 1) ? bdata(a, bi.inst, a.stage - 2) : BData{nullptr, nullptr});
     }
     if constexpr (KIND != 2) {
       if (a.src.n > 0 && g.active) add_source(a, bi, I, g, r, r0);

@@ -161,6 +161,22 @@ __device__ __forceinline__ BData bdata(const KArgs& a, int inst, int j) {
                a.bw + static_cast<int64_t>(inst) * 6 * BW_STAGES * MAX_SRC + j * MAX_SRC};
 }
 
+// The time-dependent exterior state (FP64) of variable v at face point b of
+// boundary face fc of side f (nfp points per face, nv variables).  Not
+// inlined: only boundary cells of sides with such data call it, and inlined
+// its index arithmetic and term loop took the 2D Q^2 Euler final stage from
+// 244 to 272 registers (one wavefront per SIMD instead of two) although
+// periodic meshes never run it.
+__device__ __attribute__((noinline)) inline double boundary_value(const BData& bd, int f, int64_t fc, int nfp,
+                                                                  int nv, int b, int v) {
+  const BSide& bs = bd.side[f];
+  const double* w = bd.w + f * (BW_STAGES * MAX_SRC);
+  double x = 0.0;
+  for (int q = 0; q < bs.n_terms; ++q)
+    x = fma(w[q], bs.val[((static_cast<int64_t>(q) * bs.n_faces + fc) * nfp + b) * nv + v], x);
+  return x;
+}
+
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
@@ -1020,22 +1036,14 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
   }
 
   // the time-dependent exterior state (FP64) of variable v at face point b
-  // of side f of the cell at p.  Not inlined: only boundary cells of sides
-  // with such data call it, and inlined its index arithmetic and term loop
-  // took the 2D Q^2 Euler final stage from 244 to 272 registers (one
-  // wavefront per SIMD instead of two) although periodic meshes never run it.
-  __device__ __attribute__((noinline)) static double bvalue(int f, const CellPos& p, const InstDev& I,
-                                                            const BData& bd, int b, int v) {
-    const BSide& bs = bd.side[f];
-    const double* w = bd.w + f * (BW_STAGES * MAX_SRC);
+  // of side f of the cell at p
+  __device__ __forceinline__ static double bvalue(int f, const CellPos& p, const InstDev& I, const BData& bd,
+                                                  int b, int v) {
     const int d = f / 2;
     const int64_t fc = (d == 0) ? p.y + static_cast<int64_t>(I.n[1]) * p.z
                      : (d == 1) ? p.x + static_cast<int64_t>(I.n[0]) * p.z
                                 : p.x + static_cast<int64_t>(I.n[0]) * p.y;
-    double x = 0.0;
-    for (int q = 0; q < bs.n_terms; ++q)
-      x = fma(w[q], bs.val[((static_cast<int64_t>(q) * bs.n_faces + fc) * S::NFP + b) * V + v], x);
-    return x;
+    return boundary_value(bd, f, fc, S::NFP, V, b, v);
   }
   // exterior traces of side f from its time-dependent data
   __device__ __forceinline__ static void boundary_data(int f, const CellPos& p, const InstDev& I,

@@ -935,7 +935,8 @@ int crkdg_set_boundary_data(crkdg_mesh* m, int32_t inst, int32_t side, int32_t n
   if (m->live_graphs > 0)
     return fail(CRKDG_E_ARG, "step graphs of this mesh are alive: they hold the previous boundary data");
   const Group& g = m->groups[m->inst[inst].group];
-  if (g.ops->coop) return fail(CRKDG_E_UNSUPPORTED, "time-dependent boundary data: not built for this variant");
+  if (g.ops->coop && p.dim == 3)
+    return fail(CRKDG_E_UNSUPPORTED, "time-dependent boundary data: not built for this variant");
   for (int j = 0; j < 3 * n_terms; ++j)
     if (!std::isfinite(coef[j])) return fail(CRKDG_E_ARG, "non-finite coefficient");
   if (int rc = set_device(m)) return rc;
