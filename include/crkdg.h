@@ -70,8 +70,7 @@ extern "C" {
 #define CRKDG_BC_DIRICHLET 3 /* exterior trace = the prescribed state bc_state of the side
                                 (Dirichlet and inflow sides of Sec. 4) */
 /* Reflective and Dirichlet sides enter only the final stage (the inner stages
- * use no exterior data).  They are not built for 2D Q^3 Euler in FP64:
- * crkdg_init_mesh returns CRKDG_E_UNSUPPORTED there. */
+ * use no exterior data); every compiled family has them. */
 
 #define CRKDG_SYS_ADVECTION 0 /* f(u) = a u, scalar */
 #define CRKDG_SYS_BURGERS 1   /* f_d(u) = u^2 / 2, scalar */
@@ -234,8 +233,8 @@ const char *crkdg_last_error(void);
  * invalid problem, CRKDG_E_UNSUPPORTED for a combination not compiled,
  * CRKDG_E_HIP.  Compiled, each in FP64 and mixed form: 1D P^1-P^3 (all
  * systems); 2D Q^1-Q^3 and P^1-P^3 (advection, Euler); 3D Q^1 and P^1
- * (advection, Euler), Q^2 and P^2 advection, Q^2 Euler; 3D P^2 Euler in the
- * mixed form only.  Burgers is 1D only.  Shallow water: 1D P^1-P^3 and 2D Q^1-Q^3, P^1-P^3,
+ * (advection, Euler), Q^2 and P^2 advection, Q^2, P^2 and P^3 Euler.
+ * Burgers is 1D only.  Shallow water: 1D P^1-P^3 and 2D Q^1-Q^3, P^1-P^3,
  * FP64 and mixed. */
 int crkdg_init_mesh(const crkdg_problem *problems, int32_t n_inst, crkdg_mesh **out,
                     crkdg_layout *layout);
@@ -295,8 +294,7 @@ int crkdg_set_source(crkdg_mesh *mesh, int32_t n_terms, const crkdg_state *terms
  * of the cRKDG scheme use no boundary data).  The side must be Dirichlet;
  * its bc_state still serves the admissibility check at mesh creation.  The
  * mesh keeps the pointer; n_terms = 0 returns the side to its constant
- * state.  Refused while step graphs of the mesh exist (CRKDG_E_ARG) and for
- * the cooperative 3D Q^2 Euler kernels (CRKDG_E_UNSUPPORTED).
+ * state.  Refused while step graphs of the mesh exist (CRKDG_E_ARG).
  * Synchronous. */
 int crkdg_set_boundary_data(crkdg_mesh *mesh, int32_t inst, int32_t side, int32_t n_terms, const double *coef,
                             const double *values);

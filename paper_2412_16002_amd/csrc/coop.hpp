@@ -1,4 +1,5 @@
-// Cooperative stage kernels for the tensor-product spaces Q^k in 2D and 3D.
+// Cooperative stage kernels for the tensor-product spaces Q^k in 2D and 3D,
+// and for the total-degree spaces P^k as subspaces of Q^k.
 //
 // One workgroup owns a tile of 64 cells (TX x TY x TZ) and has one wavefront
 // per conserved variable: lane l of wavefront v holds the modes of variable v
@@ -17,6 +18,13 @@
 // the outside cell's trace from that cell's modes in memory (a halo), with the
 // same operations as an own trace, so the two tiles sharing such a face form
 // bitwise the same flux and the averages stay conservative.
+//
+// P^k (Sec. 2, the spaces of the DG method) runs through the same arithmetic:
+// its Legendre modes are the Q^k modes of total degree <= k, the quadrature
+// rules are the same tensor rules, and the modes are orthogonal under them,
+// so the P^k residual of a P^k state is the Q^k residual of the same state
+// (zero in the other modes) restricted to the P^k modes.  Those other modes
+// are compile-time zeros on input and never stored.
 //
 // The stage semantics are those of stage_local_item / stage_final_item
 // (Scheme 1L of Appendix B, the checks of Sec. 4.1, the limiter of Sec. 2.2
@@ -196,17 +204,18 @@ __device__ __forceinline__ void along2(const T (&x1)[ipow(N, ND)], const T (&x2)
   });
 }
 
-template <int D, int K, int SYS, typename T, int TX, int TY, int TZ>
+template <int D, int K, int SP, int SYS, typename T, int TX, int TY, int TZ>
 struct Coop {
-  using S = Space<D, K, SP_Q>;
+  using S = Space<D, K, SP_Q>;    // the tensor space the arithmetic runs in
+  using SS = Space<D, K, SP>;     // the stored space (Q^k, or P^k inside it)
   using P = Phys<D, SYS>;
   using O1 = Op1<K, T>;
-  using CellT = Cell<D, K, SP_Q, SYS, T>;
+  using CellT = Cell<D, K, SP, SYS, T>;
   using Rec = typename CellT::Record;
   static constexpr int V = P::V;
   static constexpr int N = K + 1;
-  static constexpr int M = S::M;
-  static constexpr int MH = M - 1;
+  static constexpr int M = S::M;       // tensor modes per variable (registers)
+  static constexpr int MH = SS::M - 1; // stored modes >= 1 per variable (memory)
   static constexpr int NQ = S::NQ;
   static constexpr int NFP = S::NFP;
   static constexpr int NL = O1::NL;
@@ -226,7 +235,38 @@ struct Coop {
   static constexpr int nfd(int d) { return (tdim(d) + 1) * tsz1(d) * tsz2(d); }
   static constexpr int cmax(int a, int b) { return a > b ? a : b; }
   static constexpr int NF_MAX = cmax(cmax(nfd(0), nfd(1)), D == 3 ? nfd(2) : 0);
-  static constexpr int LDS_T = cmax(cmax(V * NQ * 64, V * NFP * 2 * NF_MAX), V * NPF * 64);
+  // the volume point values of all variables go through LDS at once, or
+  // (when that would exceed 72 KiB: Q^3 in 3D, where it would leave room
+  // for one workgroup per CU or none) one slab of the last direction at a
+  // time
+  static constexpr bool SLAB = D == 3 && V * NQ * 64 * sizeof(T) > 72 * 1024;
+  static constexpr int NQL = SLAB ? NQ / N : NQ;    // volume points per LDS pass
+  static constexpr int LDS_T = cmax(cmax(V * NQL * 64, V * NFP * 2 * NF_MAX), V * NPF * 64);
+
+  // stored index of tensor mode m (exponents m % N, (m / N) % N, m / N^2),
+  // -1 for a mode outside the stored space
+  struct SMap {
+    int s[M];
+    constexpr SMap() : s{} {
+      for (int m = 0; m < M; ++m) s[m] = -1;
+      for (int p = 0; p < SS::M; ++p) s[SS::modes.e[p][0] + N * (SS::modes.e[p][1] + N * SS::modes.e[p][2])] = p;
+    }
+  };
+  static constexpr SMap smap{};
+  // face quadrature weights (tensor Gauss, summing to one; Prop. 2.1)
+  struct FaceW {
+    double w[NFP];
+    constexpr FaceW() : w{} {
+      for (int b = 0; b < NFP; ++b) {
+        double x = 1.0;
+        for (int j = 0, r = b; j < D - 1; ++j, r /= N) x *= 0.5 * Gauss<N>::w[r % N];
+        w[b] = x;
+      }
+    }
+  };
+  static constexpr FaceW fw{};
+  // a mode >= 1 of the stored space: one whose residual is formed
+  static constexpr bool live(int m) { return smap.s[m] > 0; }
 
   // non-negative T values ordered by their bits: LDS max of wave speeds
   using AB = typename std::conditional<MIXED, unsigned, unsigned long long>::type;
@@ -274,8 +314,12 @@ struct Coop {
     c0 = ld(avg + v * nc, c);
     cm[0] = T(c0);
     const T* h = hi + static_cast<int64_t>(v) * MH * nc;
-#pragma unroll
-    for (int m = 1; m < M; ++m) cm[m] = ld(h + (m - 1) * nc, c);
+    static_for<M - 1>([&](auto MM) {
+      constexpr int m = decltype(MM)::value + 1;
+      constexpr int p = smap.s[m];
+      if constexpr (p > 0) cm[m] = ld(h + (p - 1) * nc, c);
+      else cm[m] = T(0);
+    });
   }
 
   // trace values of a cell on its two faces normal to d (tangential index
@@ -361,8 +405,9 @@ struct Coop {
   __device__ __forceinline__ static void volume(const Geo& g, const double* avg, const T* hi, const InstDev& I,
                                                 double scale, T (&r)[M], Smem& sm) {
     auto ev = [](const T (&x)[N], T (&y)[N]) { O1::eval(x, y); };
+    T t2[M];   // with slabs: the x and y passes, kept for the z node of each slab
     {
-      T cm[M], t1[M], t2[M];
+      T cm[M], t1[M];
       double c0;
       if (g.active) load_var(avg, hi, I.ncell, g.c, g.v, cm, c0);
       else
@@ -373,13 +418,13 @@ struct Coop {
       if constexpr (D == 2) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) lds(sm)[(g.v * NQ + q) * 64 + g.lane] = t2[q];
-      } else {
+      } else if constexpr (!SLAB) {
         along<N, D, 2>(t2, t1, ev);
 #pragma unroll
         for (int q = 0; q < NQ; ++q) lds(sm)[(g.v * NQ + q) * 64 + g.lane] = t1[q];
       }
     }
-    __syncthreads();
+    if constexpr (!SLAB) __syncthreads();
     // this variable's flux components, scaled by scale * 2 / dx_d; the
     // transposed passes sum_d (Dv along d) x (W along the others), slab by
     // slab of the last direction so that few partial sums are live
@@ -404,11 +449,23 @@ struct Coop {
 #pragma unroll
           for (int b = 0; b < N; ++b) {
             const int m = a + N * b;
-            if (m == 0) continue;
+            if (!live(m)) continue;
             if (O1::L.W[b][k] != 0.0) r[m] = fma(T(O1::L.W[b][k]), gx[a], r[m]);
             if (O1::L.Dv[b][k] != 0.0) r[m] = fma(T(O1::L.Dv[b][k]), gy[a], r[m]);
           }
       } else {
+        if constexpr (SLAB) {
+          // the point values of z node k: one slab of every variable in LDS
+#pragma unroll
+          for (int q = 0; q < N * N; ++q) {
+            T u = T(O1::L.P[k][0]) * t2[q];
+#pragma unroll
+            for (int c = 1; c < N; ++c) u = fma(T(O1::L.P[k][c]), t2[q + N * N * c], u);
+            lds(sm)[(g.v * NQL + q) * 64 + g.lane] = u;
+          }
+          __syncthreads();
+        }
+        constexpr int qk = SLAB ? 0 : N * N * k;   // first point of the slab in LDS
         // x pass of the three components on every x line of the slab
         T gx[N][N], gy[N][N], gz[N][N];   // [y node][x mode]
 #pragma unroll
@@ -417,7 +474,7 @@ struct Coop {
 #pragma unroll
           for (int i = 0; i < N; ++i) {
             T fd[D];
-            flux_at(g, i + N * j + N * N * k, I, sd, fd, sm);
+            flux_at(g, i + N * j + qk, I, sd, fd, sm);
             fx[i] = fd[0];
             fy[i] = fd[1];
             fz[i] = fd[2];
@@ -446,15 +503,16 @@ struct Coop {
 #pragma unroll
             for (int c = 0; c < N; ++c) {
               const int m = a + N * b + N * N * c;
-              if (m == 0) continue;
+              if (!live(m)) continue;
               if (O1::L.W[c][k] != 0.0) r[m] = fma(T(O1::L.W[c][k]), A, r[m]);
               if (O1::L.Dv[c][k] != 0.0) r[m] = fma(T(O1::L.Dv[c][k]), B[b], r[m]);
             }
           }
         }
+        if constexpr (SLAB) __syncthreads();   // the slab is read before the next one is written
       }
     });
-    __syncthreads();
+    if constexpr (!SLAB) __syncthreads();
   }
 
   // this variable's flux components (all directions, scaled by sd) at
@@ -465,7 +523,7 @@ struct Coop {
                                                  T (&fd)[D], const Smem& sm) {
     T u[V];
 #pragma unroll
-    for (int w = 0; w < V; ++w) u[w] = lds(sm)[(w * NQ + q) * 64 + g.lane];
+    for (int w = 0; w < V; ++w) u[w] = lds(sm)[(w * NQL + q) * 64 + g.lane];
     if constexpr (SYS == SYS_EULER) {
       if (g.v == 0) {
         // mass flux m_d
@@ -644,7 +702,7 @@ struct Coop {
       double slo = 0.0, sup = 0.0;
 #pragma unroll
       for (int b = 0; b < NFP; ++b) {
-        const double wb = S::tab.wb[b];
+        const double wb = fw.w[b];
         slo = fma(wb, static_cast<double>(flo[b]), slo);
         sup = fma(wb, static_cast<double>(fup[b]), sup);
       }
@@ -674,7 +732,7 @@ struct Coop {
 #pragma unroll
         for (int a = 0; a < N; ++a) {
           const int m = base + a * sdd;
-          if (m == 0) continue;
+          if (!live(m)) continue;
           const T k = T(-(2.0 * a + 1.0)) * sct;
           r[m] = fma(k, (a & 1) ? Sx : Dx, r[m]);
         }
@@ -704,18 +762,17 @@ struct Coop {
     }
     if (ghost_lo) ghost(2 * d, I, uR, uL);
     if (ghost_up) ghost(2 * d + 1, I, uL, uR);
-    if constexpr (D == 2) {
-      // time-dependent Dirichlet data (2D variants only; boundary face
-      // index along the tangential direction)
-      const int f = ghost_lo ? 2 * d : 2 * d + 1;
-      if (bd.side && (ghost_lo || ghost_up) && (I.bdyn & (1u << f))) {
-        const int64_t fc = g.o[oax1(d)] + q1;
+    // time-dependent Dirichlet data: the boundary face index runs over the
+    // tangential cell coordinates, the lower direction fastest
+    const int f = ghost_lo ? 2 * d : 2 * d + 1;
+    if (bd.side && (ghost_lo || ghost_up) && (I.bdyn & (1u << f))) {
+      int64_t fc = g.o[oax1(d)] + q1;
+      if constexpr (D == 3) fc += static_cast<int64_t>(I.n[oax1(d)]) * (g.o[oax2(d)] + q2);
 #pragma unroll
-        for (int w = 0; w < V; ++w) {
-          const T x = T(boundary_value(bd, f, fc, NFP, V, b, w));
-          if (ghost_lo) uL[w] = x;
-          else uR[w] = x;
-        }
+      for (int w = 0; w < V; ++w) {
+        const T x = T(boundary_value(bd, f, fc, NFP, V, b, w));
+        if (ghost_lo) uL[w] = x;
+        else uR[w] = x;
       }
     }
     return true;
@@ -794,8 +851,10 @@ struct Coop {
       r0 = fma(kap[p], ld(a.src.avg[p] + I.avg_off + g.v * nc, g.c), r0);
       const T kt = T(kap[p]);
       const T* h = static_cast<const T*>(a.src.hi[p]) + I.hi_off + static_cast<int64_t>(g.v) * MH * nc;
-#pragma unroll
-      for (int m = 1; m < M; ++m) r[m] = fma(kt, ld(h + (m - 1) * nc, g.c), r[m]);
+      static_for<M - 1>([&](auto MM) {
+        constexpr int m = decltype(MM)::value + 1;
+        if constexpr (live(m)) r[m] = fma(kt, ld(h + (smap.s[m] - 1) * nc, g.c), r[m]);
+      });
     }
   }
 
@@ -842,8 +901,7 @@ struct Coop {
         int tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
         const Geo gj = geo(bi, I, tid);
-        op<true>(gj, j_avg, j_hi, I, dt * a.b[j - 1], ag, r, r0, sm,
-                 D == 2 ? bdata(a, bi.inst, j - 1) : BData{nullptr, nullptr});
+        op<true>(gj, j_avg, j_hi, I, dt * a.b[j - 1], ag, r, r0, sm, bdata(a, bi.inst, j - 1));
       });
     } else {
       const int sl_in = (cur + a.stage - 2) % nsl;
@@ -851,7 +909,7 @@ struct Coop {
       const double* in_avg = sel_avg(a.slots, sl_in) + I.avg_off;
       const T* in_hi = hi_ptr<T>(sel_hi(a.slots, sl_in), I.hi_off);
       op<KIND == 1>(g, in_avg, in_hi, I, dt * a.a, ag, r, r0, sm,
-                    (D == 2 && KIND == 1) ? bdata(a, bi.inst, a.stage - 2) : BData{nullptr, nullptr});
+                    KIND == 1 ? bdata(a, bi.inst, a.stage - 2) : BData{nullptr, nullptr});
     }
     if constexpr (KIND != 2) {
       if (a.src.n > 0 && g.active) add_source(a, bi, I, g, r, r0);
@@ -866,7 +924,7 @@ struct Coop {
       o0 = o0 + r0;
       oc[0] = T(o0);
 #pragma unroll
-      for (int m = 1; m < M; ++m) oc[m] = oc[m] + r[m];
+      for (int m = 1; m < M; ++m) oc[m] = live(m) ? oc[m] + r[m] : T(0);
     } else {
 #pragma unroll
       for (int m = 0; m < M; ++m) oc[m] = T(0);
@@ -886,7 +944,8 @@ struct Coop {
     {
       T rs = T(0);
 #pragma unroll
-      for (int m = 1; m < M; ++m) rs += fabs(oc[m]);
+      for (int m = 1; m < M; ++m)
+        if (live(m)) rs += fabs(oc[m]);
       sm.avg[g.v][g.lane] = o0;
       sm.rsum[g.v][g.lane] = rs;
     }
@@ -986,8 +1045,10 @@ struct Coop {
     if (g.active && !queue) {
       st(o_avg + g.v * nc, g.c, o0);
       T* h = o_hi + static_cast<int64_t>(g.v) * MH * nc;
-#pragma unroll
-      for (int m = 1; m < M; ++m) st(h + (m - 1) * nc, g.c, oc[m]);
+      static_for<M - 1>([&](auto MM) {
+        constexpr int m = decltype(MM)::value + 1;
+        if constexpr (live(m)) st(h + (smap.s[m] - 1) * nc, g.c, oc[m]);
+      });
     }
     // queued cells: one record each, limited by the queue kernel
     if (g.v == 0 && queue) sm.qidx[g.lane] = atomicAdd(a.qcount, 1u);
@@ -1001,8 +1062,10 @@ struct Coop {
           rec->cell = static_cast<int32_t>(g.c);
         }
         rec->ub[g.v] = o0;
-#pragma unroll
-        for (int m = 1; m < M; ++m) rec->ch[g.v][m - 1] = oc[m];
+        static_for<M - 1>([&](auto MM) {
+          constexpr int m = decltype(MM)::value + 1;
+          if constexpr (live(m)) rec->ch[g.v][smap.s[m] - 1] = oc[m];
+        });
       }
     }
     if (g.v == 0) {
@@ -1062,10 +1125,10 @@ constexpr int coop_waves_per_eu() {
 
 // One workgroup (one wavefront per variable) per tile of the stage map.
 // KIND 0: inner stage with G; 1: inner stage with F (standard RKDG); 2: final stage.
-template <int D, int K, int SYS, typename T, int TX, int TY, int TZ, int KIND>
+template <int D, int K, int SP, int SYS, typename T, int TX, int TY, int TZ, int KIND>
 __global__ __launch_bounds__((64 * Phys<D, SYS>::V)) __attribute__((amdgpu_waves_per_eu(
     coop_waves_per_eu<T, KIND>()))) void k_coop_stage(KArgs a) {
-  using C = Coop<D, K, SYS, T, TX, TY, TZ>;
+  using C = Coop<D, K, SP, SYS, T, TX, TY, TZ>;
   __shared__ typename C::Smem sm;
   if (static_cast<int>(blockIdx.x) >= a.n_items) return;
   // the tile, the instance's constants and the controller's state are

@@ -20,7 +20,7 @@ using namespace crkdg;
 namespace {
 
 using Registry = int (*)(const VariantOps**);
-const Registry kRegistries[] = {&variants_v1d, &variants_v2d_q_adv, &variants_v2d_p_adv, &variants_v2d_q12_euler, &variants_v2d_q3_euler, &variants_v2d_p_euler, &variants_v3d_q1, &variants_v3d_q2_adv, &variants_v3d_q2_euler, &variants_v3d_p, &variants_v3d_p2_euler, &variants_swe_1d_q, &variants_swe_2d_p};
+const Registry kRegistries[] = {&variants_v1d, &variants_v2d_q_adv, &variants_v2d_p_adv, &variants_v2d_q12_euler, &variants_v2d_q3_euler, &variants_v2d_p_euler, &variants_v3d_q1, &variants_v3d_q2_adv, &variants_v3d_q2_euler, &variants_v3d_p, &variants_v3d_p2_euler, &variants_v3d_p3_euler, &variants_swe_1d_q, &variants_swe_2d_p};
 
 thread_local std::string g_err = "";
 
@@ -602,7 +602,7 @@ int crkdg_init_mesh(const crkdg_problem* problems, int32_t n_inst, crkdg_mesh** 
             delete m;
             return fail(CRKDG_E_UNSUPPORTED, "problem " + std::to_string(i) +
                                                  ": reflective and Dirichlet sides are not built for this "
-                                                 "dim/k/space/system/precision (2D Q^3 Euler FP64)");
+                                                 "dim/k/space/system/precision");
           }
     if (!ops->alpha_modes && p.alpha != CRKDG_ALPHA_FACE) {
       delete m;
@@ -934,9 +934,6 @@ int crkdg_set_boundary_data(crkdg_mesh* m, int32_t inst, int32_t side, int32_t n
   if (n_terms > 0 && (!coef || !d_values)) return fail(CRKDG_E_ARG, "NULL coef or values");
   if (m->live_graphs > 0)
     return fail(CRKDG_E_ARG, "step graphs of this mesh are alive: they hold the previous boundary data");
-  const Group& g = m->groups[m->inst[inst].group];
-  if (g.ops->coop && p.dim == 3)
-    return fail(CRKDG_E_UNSUPPORTED, "time-dependent boundary data: not built for this variant");
   for (int j = 0; j < 3 * n_terms; ++j)
     if (!std::isfinite(coef[j])) return fail(CRKDG_E_ARG, "non-finite coefficient");
   if (int rc = set_device(m)) return rc;

@@ -71,24 +71,25 @@ template <int D, int K, int SP, int SYS, typename T> struct Ops {
   }
 };
 
-// A variant whose stage kernels are the cooperative ones (tensor spaces, 2D
-// and 3D): every boundary kind and alpha mode is built in; the limiter,
-// wave-speed, projection and queue kernels stay the one-thread-per-cell ones.
-template <int D, int K, int SYS, typename T, int TX, int TY, int TZ> struct OpsCoop {
-  using B = Ops<D, K, SP_Q, SYS, T>;
+// A variant whose stage kernels are the cooperative ones (tensor spaces in 2D
+// and 3D, and P^k inside Q^k): every boundary kind and alpha mode is built
+// in; the limiter, wave-speed, projection and queue kernels stay the
+// one-thread-per-cell ones of the stored space.
+template <int D, int K, int SYS, typename T, int TX, int TY, int TZ, int SP = SP_Q> struct OpsCoop {
+  using B = Ops<D, K, SP, SYS, T>;
   static constexpr int NT = 64 * Phys<D, SYS>::V;
   static void local(const KArgs& a, int nb, int, hipStream_t s) {
-    hipLaunchKernelGGL((k_coop_stage<D, K, SYS, T, TX, TY, TZ, 0>), dim3(nb), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((k_coop_stage<D, K, SP, SYS, T, TX, TY, TZ, 0>), dim3(nb), dim3(NT), 0, s, a);
   }
   static void inner_dg(const KArgs& a, int nb, int, hipStream_t s) {
-    hipLaunchKernelGGL((k_coop_stage<D, K, SYS, T, TX, TY, TZ, 1>), dim3(nb), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((k_coop_stage<D, K, SP, SYS, T, TX, TY, TZ, 1>), dim3(nb), dim3(NT), 0, s, a);
   }
   static void final_(const KArgs& a, int nb, int, hipStream_t s) {
-    hipLaunchKernelGGL((k_coop_stage<D, K, SYS, T, TX, TY, TZ, 2>), dim3(nb), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL((k_coop_stage<D, K, SP, SYS, T, TX, TY, TZ, 2>), dim3(nb), dim3(NT), 0, s, a);
   }
   static VariantOps make() {
-    using C = Cell<D, K, SP_Q, SYS, T>;
-    return VariantOps{D, K, SP_Q, SYS, sizeof(T) == 8 ? CRKDG_FP64 : CRKDG_MIXED,
+    using C = Cell<D, K, SP, SYS, T>;
+    return VariantOps{D, K, SP, SYS, sizeof(T) == 8 ? CRKDG_FP64 : CRKDG_MIXED,
                       C::M, C::V, C::S::NQ, C::NS, static_cast<int>(sizeof(typename C::Record)), 1, 1,
                       nullptr, nullptr, &B::limit, &B::cfl, &B::project, &B::queue_local, &B::queue_final,
                       nullptr, nullptr, nullptr, nullptr,
@@ -108,6 +109,7 @@ int variants_v3d_q2_adv(const VariantOps** out);
 int variants_v3d_q2_euler(const VariantOps** out);
 int variants_v3d_p(const VariantOps** out);
 int variants_v3d_p2_euler(const VariantOps** out);
+int variants_v3d_p3_euler(const VariantOps** out);
 int variants_swe_1d_q(const VariantOps** out);
 int variants_swe_2d_p(const VariantOps** out);
 

@@ -1,11 +1,12 @@
-// Compiled variant: 3D P^2 (total degree) Euler, mixed precision only.  The
-// FP64 form, fully unrolled, spills ~3.5 KB per lane and is not built; the
-// mixed form keeps its state in VGPRs and AGPRs (one wavefront per SIMD).
+// Compiled variants: 3D P^2 (total degree) Euler, FP64 and mixed precision:
+// the cooperative stage kernels of Q^2 on 16 x 2 x 2 tiles with the modes
+// outside P^2 held at zero and never stored.
 #include "variants.hpp"
 
 namespace crkdg {
 static const VariantOps kOps[] = {
-    Ops<3, 2, SP_P, SYS_EULER, float>::make(),
+    OpsCoop<3, 2, SYS_EULER, double, 16, 2, 2, SP_P>::make(),
+    OpsCoop<3, 2, SYS_EULER, float, 16, 2, 2, SP_P>::make(),
 };
 int variants_v3d_p2_euler(const VariantOps** out) {
   *out = kOps;

@@ -380,6 +380,31 @@ def mms_euler2d_scenario2_box(k, level, space="P", precision="fp64"):
                 meta=dict(dt=dt, bc_coef=SCENARIO2_COEF, bc_terms=scenario2_boundary_terms()))
 
 
+def euler_wave_box3d(k, n, space="Q", precision="fp64", amp=0.5, gamma=GAMMA):
+    """The 3D density wave rho = 1 + amp sin(2 pi (x + y + z - 3 t)), w = (1,
+    1, 1), p = 1 on [0, 1]^3 with its exact values as Dirichlet data on the
+    four x and y sides (z periodic).  The data are three time-separable terms
+    (U is affine in rho): a constant, sin(2 pi s) cos(6 pi t) and
+    cos(2 pi s) cos(6 pi t + pi / 2), s = x + y + z."""
+    def exact(X, t):
+        X = np.asarray(X)
+        rho = 1.0 + amp * np.sin(2.0 * np.pi * (np.sum(X, axis=-1) - 3.0 * t))
+        return conservative(rho, np.ones(X.shape[:-1] + (3,)), np.ones(X.shape[:-1]))
+
+    lin = np.array([1.0, 1.0, 1.0, 1.0, 1.5])                   # dU / drho
+    base = np.array([1.0, 1.0, 1.0, 1.0, 1.0 / (gamma - 1.0) + 1.5])
+    terms = [lambda X: np.broadcast_to(base, X.shape[:-1] + (5,)),
+             lambda X: amp * np.sin(2.0 * np.pi * np.sum(X, axis=-1))[..., None] * lin,
+             lambda X: amp * np.cos(2.0 * np.pi * np.sum(X, axis=-1))[..., None] * lin]
+    coef = ((0.0, 0.0, 0.0), (0.0, 6.0 * math.pi, 0.0), (0.0, 6.0 * math.pi, 0.5 * math.pi))
+    st = [float(v) for v in exact(np.zeros((1, 3)), 0.0)[0]]
+    params = dict(dim=3, n=tuple(n), system="euler", k=k, space=space, stages=k + 1, cfl=0.1, eps=1e-8,
+                  bc=("dirichlet", "dirichlet", "periodic"), bc_state={f: st for f in range(4)},
+                  precision=precision)
+    return Case(f"euler_wave_box3d_{space}{k}", params, u0=lambda X: exact(X, 0.0), t_end=0.01, exact=exact,
+                meta=dict(bc_coef=coef, bc_terms=terms))
+
+
 def table1_advection(k, level, precision="fp64"):
     """Example 4.1: u_t + u_x = 0 on [0, 1], u = sin(2 pi (x - t)) + 2 in [1, 3],
     the meshes and steps of Table 1 (dt = 2^(4-level) 1e-4, dx = 1/2^(level +

@@ -6,7 +6,8 @@ library their time-separable terms at the face points); Example 4.1 on the
 meshes and steps of Table 1 with its exact inflow (errors equal to the
 oracle's, rates k+1); Example 4.2 scenario II on the paper's [0, 1]^2 with
 exact data on all sides (Table 3's meshes and steps; 2D Q^3 runs the
-cooperative kernels)."""
+cooperative kernels); the 3D density wave with exact data on its x and y
+sides through the 3D cooperative kernels (Q^2, P^2, P^3)."""
 import itertools
 import math
 import sys
@@ -52,11 +53,15 @@ CASES = {"table1_p2": (lambda: inputs.table1_advection(2, 0), [0]),
          "scenario2_q3": (lambda: inputs.mms_euler2d_scenario2_box(3, 0, "Q"), [0, 1, 2, 3]),
          "table1_p3": (lambda: inputs.table1_advection(3, 1), [0]),
          "scenario2_p2": (lambda: inputs.mms_euler2d_scenario2_box(2, 0, "P"), [0, 1, 2, 3]),
-         "scenario2_q1": (lambda: inputs.mms_euler2d_scenario2_box(1, 0, "Q"), [0, 1, 2, 3])}
+         "scenario2_q1": (lambda: inputs.mms_euler2d_scenario2_box(1, 0, "Q"), [0, 1, 2, 3]),
+         # 3D cooperative kernels (tiles of 16 x 2 x 2 cells, ragged in every direction)
+         "wave3d_q2": (lambda: inputs.euler_wave_box3d(2, (19, 5, 3), "Q"), [0, 1, 2, 3]),
+         "wave3d_p2": (lambda: inputs.euler_wave_box3d(2, (19, 5, 3), "P"), [0, 1, 2, 3]),
+         "wave3d_p3": (lambda: inputs.euler_wave_box3d(3, (19, 5, 3), "P"), [0, 1, 2, 3])}
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
-@pytest.mark.parametrize("name", list(CASES) + ["scenario2_p2_rkdg", "scenario2_q3_rkdg"])
+@pytest.mark.parametrize("name", list(CASES) + ["scenario2_p2_rkdg", "scenario2_q3_rkdg", "wave3d_q2_rkdg"])
 def test_boundary_data_stage_parity(lib, name, precision):
     """Every stage from a nonzero t^n; the _rkdg cases run standard RKDG,
     whose inner stages apply F (with the data at their own stage times)."""

@@ -63,6 +63,12 @@ CASES = {
     "euler3d_q2_sides": dict(dim=3, n=(9, 6, 5), system="euler", k=2, stages=4, cfl=0.15,
                              bc=("reflect", "periodic", "dirichlet"), bc_upper=("reflect", "periodic", "outflow"),
                              bc_state={4: _cons(1.2, [0.0, 0.2, 0.4], 0.9)}),
+    "euler3d_p2_sides": dict(dim=3, n=(19, 5, 3), system="euler", k=2, space="P", stages=3, cfl=0.15,
+                             bc=("dirichlet", "reflect", "periodic"), bc_upper=("reflect", "outflow", "periodic"),
+                             bc_state={0: _cons(0.8, [0.4, -0.1, 0.2], 1.0)}),
+    "euler3d_p3_sides": dict(dim=3, n=(19, 5, 3), system="euler", k=3, space="P", stages=4, cfl=0.09,
+                             bc=("periodic", "reflect", "dirichlet"), bc_upper=("periodic", "reflect", "outflow"),
+                             bc_state={4: _cons(1.1, [0.1, 0.0, 0.3], 0.9)}),
     "euler2d_q3_walls": dict(dim=2, n=(13, 11), system="euler", k=3, stages=4, cfl=0.09,
                              bc=("reflect", "dirichlet"), bc_upper=("outflow", "reflect"),
                              bc_state={2: _cons(0.7, [0.1, 0.2], 0.6)}),

@@ -1,0 +1,82 @@
+"""3D P^2 and P^3 (total degree) Euler, FP64 and mixed precision, through the
+cooperative tensor kernels (P^k held inside Q^k): three controller steps of
+the mixed form against the FP64 oracle, and the exact density wave at three
+resolutions in both forms.  Stage, limiter, step, boundary, alpha and
+standard-RKDG parity of the same families run with the other families'
+(test_gpu_parity, test_gpu_mixed_parity, test_gpu_boundaries,
+test_gpu_alpha, test_gpu_rkdg)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from _helpers import gpu_problem, oracle_problem, random_state, rel_err_per_var, round_hi
+from test_gpu_parity import CASES
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2412_16002_amd import crkdg
+    return crkdg
+
+
+@pytest.mark.parametrize("name", ["euler3d_p2", "euler3d_p3"])
+def test_mixed_step_parity(lib, name):
+    """Three accepted steps of the mixed form through the device controller
+    against the oracle's FP64 steps (1e-5 of the variable's magnitude),
+    totals conserved."""
+    params = dict(CASES[name], precision="mixed")
+    o, mesh = oracle.CRKDG(oracle_problem(params)), lib.Mesh(gpu_problem(params))
+    C0 = round_hi(random_state(o, seed=181, rel_amp=0.1), "mixed")
+    slots = mesh.new_slots()
+    mesh.set_legendre(slots[0], C0)
+    ctl = mesh.new_ctl()
+    mesh.start(slots, ctl, t0=0.0)
+    T0 = mesh.totals(slots[0]).cpu().numpy().copy()
+    U = o.from_legendre(C0)
+    t = 0.0
+    for n in range(3):
+        _say(f"[3D P mixed step] {name} step {n}")
+        U, info_o = o.step(U, t)
+        t = info_o["t"]
+        info = mesh.step(slots, ctl)[0]
+        assert info["status"] == 0 and info["halvings"] == info_o["halvings"]
+        assert math.isclose(info["dt"], info_o["dt"], rel_tol=1e-5)
+        got = mesh.get_legendre(slots[info["cur"]])
+        err = rel_err_per_var(got, o.to_legendre(U))
+        _say(f"   dt {info['dt']:.4e} rel err {err:.2e}")
+        assert err < 1e-5
+        assert o.bound_violations(o.from_legendre(got)) == 0
+    T = mesh.totals(slots[info["cur"]]).cpu().numpy()
+    assert np.all(np.abs(T - T0) <= 1e-13 * np.maximum(np.abs(T0), 1.0))
+
+
+@pytest.mark.parametrize("k,meshes,lo", [(2, (8, 16, 32), 2.7), (3, (8, 16, 32), 3.4)])
+def test_density_wave_converges(lib, k, meshes, lo):
+    """The exact 3D density wave (rho = 1 + 0.5 sin(2 pi (x + y + z - 3t)))
+    to t = 0.01: the relative L1 error of rho falls at about order k+1 in
+    both forms, and the mixed form stays at the FP64 error."""
+    from test_gpu_convergence import _error
+    errs = {}
+    for precision in ("fp64", "mixed"):
+        errs[precision] = []
+        for n in meshes:
+            e, steps = _error(lib, 3, n, k, precision, 0.01, space="P")
+            errs[precision].append(e)
+            _say(f"[wave 3D P{k} {precision}] n = {n}: {steps} steps, relative L1 error of rho {e:.3e}")
+        rates = [math.log2(a / b) for a, b in zip(errs[precision], errs[precision][1:])]
+        _say(f"[wave 3D P{k} {precision}] rates {['%.2f' % r for r in rates]}")
+        assert rates[-1] > lo
+    for ef, em in zip(errs["fp64"], errs["mixed"]):
+        assert abs(em - ef) <= 0.05 * ef

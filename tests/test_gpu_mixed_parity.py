@@ -27,7 +27,6 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 EULER = [n for n, p in CASES.items() if p["system"] == "euler"]
-EXTRA = {"euler3d_p2": dict(dim=3, n=(7, 6, 5), system="euler", k=2, space="P", stages=3, cfl=0.15)}
 
 
 def _say(*a):
@@ -42,9 +41,9 @@ def lib():
     return crkdg
 
 
-@pytest.mark.parametrize("name", EULER + list(EXTRA))
+@pytest.mark.parametrize("name", EULER)
 def test_mixed_limit_parity(lib, name):
-    params = dict(CASES.get(name) or EXTRA[name], precision="mixed")
+    params = dict(CASES[name], precision="mixed")
     o = oracle.CRKDG(oracle_problem(params))
     mesh = lib.Mesh(gpu_problem(params))
     C = round_hi(random_state(o, seed=11, rel_amp=3.0, limited=False), "mixed")

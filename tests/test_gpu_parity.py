@@ -57,6 +57,10 @@ CASES = {
     "euler3d_p1": dict(dim=3, n=(9, 7, 8), system="euler", k=1, space="P", stages=2, cfl=0.3),
     "adv3d_p2": dict(dim=3, n=(7, 6, 5), system="advection", k=2, space="P", stages=3, vel=(1.0, 0.5, -0.3),
                      bound_lo=0.0, bound_hi=2.0, cfl=0.15),
+    # cooperative kernels on 16 x 2 x 2 tiles: two tiles along x (the second
+    # ragged), ragged along y and z
+    "euler3d_p2": dict(dim=3, n=(19, 5, 3), system="euler", k=2, space="P", stages=3, cfl=0.15),
+    "euler3d_p3": dict(dim=3, n=(19, 5, 3), system="euler", k=3, space="P", stages=4, cfl=0.09),
 }
 FP64_TOL = 1e-12
 
@@ -125,7 +129,8 @@ def test_stage_parity(lib, name):
 
 
 @pytest.mark.parametrize("name", ["burgers1d_p2", "euler1d_p3_outflow", "euler2d_q2", "euler2d_p3",
-                                  "adv2d_q2", "euler3d_q1", "euler3d_q2", "euler3d_p1", "adv3d_p2"])
+                                  "adv2d_q2", "euler3d_q1", "euler3d_q2", "euler3d_p1", "adv3d_p2",
+                                  "euler3d_p2", "euler3d_p3"])
 def test_step_parity(lib, name):
     """Three accepted steps through the device controller (adaptive dt from
     the fused wave-speed maximum) against the oracle's steps."""
@@ -153,7 +158,7 @@ def test_step_parity(lib, name):
 
 
 @pytest.mark.parametrize("name", ["burgers1d_p2", "euler1d_p3_outflow", "euler2d_q2", "euler2d_p2",
-                                  "euler3d_q1", "euler3d_q2"])
+                                  "euler3d_q1", "euler3d_q2", "euler3d_p2", "euler3d_p3"])
 def test_cfl_and_averages(lib, name):
     params, o, mesh = _setup(lib, name)
     C = random_state(o, seed=41, rel_amp=0.1)
@@ -173,7 +178,8 @@ def test_cfl_and_averages(lib, name):
     assert np.allclose(avg.cpu().numpy().reshape(o.V, o.ncell).T, o.cell_average(U), rtol=1e-14, atol=1e-15)
 
 
-@pytest.mark.parametrize("name", ["burgers1d_p2", "euler2d_q2", "euler2d_p3", "adv3d_q2", "euler3d_q2"])
+@pytest.mark.parametrize("name", ["burgers1d_p2", "euler2d_q2", "euler2d_p3", "adv3d_q2", "euler3d_q2",
+                                  "euler3d_p3"])
 def test_projection_parity(lib, name):
     params, o, mesh = _setup(lib, name)
 
@@ -198,7 +204,7 @@ def test_projection_parity(lib, name):
 
 
 @pytest.mark.parametrize("name", ["euler2d_q2", "euler2d_p3", "euler1d_p3_outflow", "burgers1d_p2",
-                                  "euler3d_q2", "euler3d_p1", "adv3d_p2"])
+                                  "euler3d_q2", "euler3d_p1", "adv3d_p2", "euler3d_p2", "euler3d_p3"])
 def test_mixed_stage_parity(lib, name):
     """Mixed precision (modes >= 1 and transforms in FP32, averages FP64): one
     stage from identical (FP32-representable) inputs within 1e-5 of the

@@ -44,7 +44,8 @@ def _states(mesh, coeffs):
 
 
 STAGE_CASES = ["burgers1d_p2", "euler1d_p3_outflow", "euler1d_p1", "euler2d_q2", "euler2d_q1_outflow",
-               "euler2d_q3", "euler2d_p3", "adv2d_q2", "euler3d_q1", "adv3d_q2", "euler3d_q2"]
+               "euler2d_q3", "euler2d_p3", "adv2d_q2", "euler3d_q1", "adv3d_q2", "euler3d_q2", "euler3d_p2",
+               "euler3d_p3"]
 
 
 @pytest.mark.parametrize("name", STAGE_CASES)
@@ -100,7 +101,7 @@ def test_rkdg_step_parity(lib, name):
         assert err < 10 * FP64_TOL
 
 
-@pytest.mark.parametrize("name", ["euler2d_q2", "euler2d_p3", "euler3d_q2"])
+@pytest.mark.parametrize("name", ["euler2d_q2", "euler2d_p3", "euler3d_q2", "euler3d_p3"])
 def test_rkdg_mixed_stage_parity(lib, name):
     """Mixed precision, standard RKDG: each stage within 1e-5 of the
     variable's magnitude (averages 1e-6) of the FP64 oracle; limited points
