@@ -616,6 +616,30 @@ struct Coop {
 #pragma unroll
         for (int b = 0; b < NFP; ++b) lds(sm)[fidx<d>(g.v, b, side, fi)] = side ? lo[b] : up[b];
       }
+      // time-dependent Dirichlet data of a mesh side the tile touches: the
+      // exterior values go into the ghost side of its boundary slots (side 0
+      // below the mesh, side 1 above it), where the flux pass reads them.
+      // Boundary face index: tangential cell coordinates, lower direction
+      // fastest.  Kept out of the flux pass: there the call would hold its
+      // registers across the whole pass.
+      if (bd.side) {
+#pragma unroll 1
+        for (int up = 0; up < 2; ++up) {
+          const int f = 2 * d + up;
+          const bool edge = up ? (g.o[d] + g.A[d] == I.n[d]) : (g.o[d] == 0);
+          if (!edge || I.bc[f] != CRKDG_BC_DIRICHLET || !(I.bdyn & (1u << f))) continue;
+          const int p = up ? g.A[d] : 0;
+#pragma unroll 1
+          for (int j = g.lane; j < T1 * T2 * NFP; j += 64) {
+            const int b = j % NFP, qq = j / NFP;
+            const int h1 = qq % T1, h2 = qq / T1;
+            if (h1 >= g.A[oax1(d)] || (D == 3 && h2 >= g.A[oax2(d)])) continue;
+            int64_t fc = g.o[oax1(d)] + h1;
+            if constexpr (D == 3) fc += static_cast<int64_t>(I.n[oax1(d)]) * (g.o[oax2(d)] + h2);
+            lds(sm)[fidx<d>(g.v, b, up, slot<d>(p, h1, h2))] = T(boundary_value(bd, f, fc, NFP, V, b, g.v));
+          }
+        }
+      }
     }
     __syncthreads();
     if constexpr (DG) {
@@ -754,27 +778,18 @@ struct Coop {
     const bool ghost_lo = (p == 0) && (g.o[d] == 0) && I.bc[2 * d] != CRKDG_BC_PERIODIC;
     const bool ghost_up = (p == g.A[d]) && (g.o[d] + p == I.n[d]) && I.bc[2 * d + 1] != CRKDG_BC_PERIODIC;
     // both sides read unconditionally (a ghost side's slot holds stale
-    // words, overwritten below)
+    // words, overwritten below, or the side's time-dependent data)
 #pragma unroll
     for (int w = 0; w < V; ++w) {
       uL[w] = lds(sm)[fidx<d>(w, b, 0, fi)];
       uR[w] = lds(sm)[fidx<d>(w, b, 1, fi)];
     }
-    if (ghost_lo) ghost(2 * d, I, uR, uL);
-    if (ghost_up) ghost(2 * d + 1, I, uL, uR);
-    // time-dependent Dirichlet data: the boundary face index runs over the
-    // tangential cell coordinates, the lower direction fastest
-    const int f = ghost_lo ? 2 * d : 2 * d + 1;
-    if (bd.side && (ghost_lo || ghost_up) && (I.bdyn & (1u << f))) {
-      int64_t fc = g.o[oax1(d)] + q1;
-      if constexpr (D == 3) fc += static_cast<int64_t>(I.n[oax1(d)]) * (g.o[oax2(d)] + q2);
-#pragma unroll
-      for (int w = 0; w < V; ++w) {
-        const T x = T(boundary_value(bd, f, fc, NFP, V, b, w));
-        if (ghost_lo) uL[w] = x;
-        else uR[w] = x;
-      }
-    }
+    // a side with time-dependent data has its exterior values in the slot
+    // already (written with the halos)
+    const bool dyn_lo = bd.side && (I.bdyn & (1u << (2 * d)));
+    const bool dyn_up = bd.side && (I.bdyn & (1u << (2 * d + 1)));
+    if (ghost_lo && !dyn_lo) ghost(2 * d, I, uR, uL);
+    if (ghost_up && !dyn_up) ghost(2 * d + 1, I, uL, uR);
     return true;
   }
 
@@ -858,7 +873,10 @@ struct Coop {
     }
   }
 
-  template <int KIND>
+  // BDY: the kernel form that reads time-dependent boundary data (launched
+  // for meshes that have some; without it the exterior states are the
+  // constant ones and no boundary-data code is compiled in)
+  template <int KIND, bool BDY>
   __device__ __forceinline__ static void run(const KArgs& a, const BlockItem& bi, const InstDev& I, crkdg_ctl* ctl,
                                              Smem& sm) {
     const Geo g = geo(bi, I, threadIdx.x);
@@ -901,7 +919,8 @@ struct Coop {
         int tid = threadIdx.x;
         asm volatile("" : "+v"(tid));
         const Geo gj = geo(bi, I, tid);
-        op<true>(gj, j_avg, j_hi, I, dt * a.b[j - 1], ag, r, r0, sm, bdata(a, bi.inst, j - 1));
+        op<true>(gj, j_avg, j_hi, I, dt * a.b[j - 1], ag, r, r0, sm,
+                 BDY ? bdata(a, bi.inst, j - 1) : BData{nullptr, nullptr});
       });
     } else {
       const int sl_in = (cur + a.stage - 2) % nsl;
@@ -909,7 +928,7 @@ struct Coop {
       const double* in_avg = sel_avg(a.slots, sl_in) + I.avg_off;
       const T* in_hi = hi_ptr<T>(sel_hi(a.slots, sl_in), I.hi_off);
       op<KIND == 1>(g, in_avg, in_hi, I, dt * a.a, ag, r, r0, sm,
-                    KIND == 1 ? bdata(a, bi.inst, a.stage - 2) : BData{nullptr, nullptr});
+                    (BDY && KIND == 1) ? bdata(a, bi.inst, a.stage - 2) : BData{nullptr, nullptr});
     }
     if constexpr (KIND != 2) {
       if (a.src.n > 0 && g.active) add_source(a, bi, I, g, r, r0);
@@ -1124,8 +1143,9 @@ constexpr int coop_waves_per_eu() {
 }
 
 // One workgroup (one wavefront per variable) per tile of the stage map.
-// KIND 0: inner stage with G; 1: inner stage with F (standard RKDG); 2: final stage.
-template <int D, int K, int SP, int SYS, typename T, int TX, int TY, int TZ, int KIND>
+// KIND 0: inner stage with G; 1: inner stage with F (standard RKDG); 2: final
+// stage.  BDY: with time-dependent boundary data (KIND 1 and 2).
+template <int D, int K, int SP, int SYS, typename T, int TX, int TY, int TZ, int KIND, bool BDY = false>
 __global__ __launch_bounds__((64 * Phys<D, SYS>::V)) __attribute__((amdgpu_waves_per_eu(
     coop_waves_per_eu<T, KIND>()))) void k_coop_stage(KArgs a) {
   using C = Coop<D, K, SP, SYS, T, TX, TY, TZ>;
@@ -1151,7 +1171,7 @@ __global__ __launch_bounds__((64 * Phys<D, SYS>::V)) __attribute__((amdgpu_waves
   crkdg_ctl* ctl = a.ctl + bi.inst;
   const CC* cc = (const CC*)ctl;
   if (cc->status != 0 || cc->accepted >= cc->goal) return;   // instance idle
-  C::template run<KIND>(a, bi, I, ctl, sm);
+  C::template run<KIND, BDY>(a, bi, I, ctl, sm);
 }
 
 }  // namespace crkdg

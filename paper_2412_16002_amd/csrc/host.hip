@@ -1121,13 +1121,17 @@ static int launch_stage(crkdg_mesh* m, int gi, int stage, const Slots& slots, cr
                        g.stages, stage, sc, m->src);
   }
   if (g.ops->coop) {
+    // meshes with time-dependent boundary data take the kernel forms that read it
+    const bool bdy = a.bside != nullptr;
     if (stage <= g.stages) {
       a.a = bt.a[stage];
-      (g.scheme == CRKDG_SCHEME_RKDG ? g.ops->coop_inner_dg : g.ops->coop_local)(a, g.n_items, g.ops->coop, s);
+      (g.scheme != CRKDG_SCHEME_RKDG ? g.ops->coop_local
+                                     : bdy ? g.ops->coop_inner_dg_bd : g.ops->coop_inner_dg)(a, g.n_items,
+                                                                                             g.ops->coop, s);
       g.ops->queue_local(a, qblocks, BLOCK, s);
     } else {
       for (int j = 0; j < 4; ++j) a.b[j] = bt.b[j];
-      g.ops->coop_final(a, g.n_items, g.ops->coop, s);
+      (bdy ? g.ops->coop_final_bd : g.ops->coop_final)(a, g.n_items, g.ops->coop, s);
       g.ops->queue_final(a, qblocks, BLOCK, s);
     }
     return CRKDG_OK;

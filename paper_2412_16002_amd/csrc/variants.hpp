@@ -24,6 +24,7 @@ struct VariantOps {
   int coop;
   int coop_tile[3];
   Launch coop_local, coop_inner_dg, coop_final;
+  Launch coop_inner_dg_bd, coop_final_bd;   // forms with time-dependent boundary data
 };
 
 template <int D, int K, int SP, int SYS, typename T> struct Ops {
@@ -67,7 +68,7 @@ template <int D, int K, int SP, int SYS, typename T> struct Ops {
                       C::ALPHA_MODES ? 1 : 0,
                       &stage_local, &stage_final, &limit, &cfl, &project, &queue_local, &queue_final,
                       &stage_local_p, &stage_final_p, &stage_inner_dg, &stage_inner_dg_p,
-                      0, {0, 0, 0}, nullptr, nullptr, nullptr};
+                      0, {0, 0, 0}, nullptr, nullptr, nullptr, nullptr, nullptr};
   }
 };
 
@@ -87,13 +88,19 @@ template <int D, int K, int SYS, typename T, int TX, int TY, int TZ, int SP = SP
   static void final_(const KArgs& a, int nb, int, hipStream_t s) {
     hipLaunchKernelGGL((k_coop_stage<D, K, SP, SYS, T, TX, TY, TZ, 2>), dim3(nb), dim3(NT), 0, s, a);
   }
+  static void inner_dg_bd(const KArgs& a, int nb, int, hipStream_t s) {
+    hipLaunchKernelGGL((k_coop_stage<D, K, SP, SYS, T, TX, TY, TZ, 1, true>), dim3(nb), dim3(NT), 0, s, a);
+  }
+  static void final_bd(const KArgs& a, int nb, int, hipStream_t s) {
+    hipLaunchKernelGGL((k_coop_stage<D, K, SP, SYS, T, TX, TY, TZ, 2, true>), dim3(nb), dim3(NT), 0, s, a);
+  }
   static VariantOps make() {
     using C = Cell<D, K, SP, SYS, T>;
     return VariantOps{D, K, SP, SYS, sizeof(T) == 8 ? CRKDG_FP64 : CRKDG_MIXED,
                       C::M, C::V, C::S::NQ, C::NS, static_cast<int>(sizeof(typename C::Record)), 1, 1,
                       nullptr, nullptr, &B::limit, &B::cfl, &B::project, &B::queue_local, &B::queue_final,
                       nullptr, nullptr, nullptr, nullptr,
-                      NT, {TX, TY, TZ}, &local, &inner_dg, &final_};
+                      NT, {TX, TY, TZ}, &local, &inner_dg, &final_, &inner_dg_bd, &final_bd};
   }
 };
 
