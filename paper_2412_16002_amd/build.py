@@ -28,6 +28,8 @@ FLAGS = [
     f"-I{ROOT / 'include'}", f"-I{CSRC}",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the compile-time basis tables of the largest spaces (3D Q^3)
+    "-fconstexpr-steps=200000000",
 ]
 
 

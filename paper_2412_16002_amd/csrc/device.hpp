@@ -382,12 +382,13 @@ template <int D, int K, int SP, int SYS, typename T> struct Cell {
   static constexpr int NS = S::NS;
   static constexpr bool MIXED = sizeof(T) == 4;
 
-  // Large spaces (3D Q^2 and P^3 Euler: 27 or 20 modes x 5 variables) keep
-  // their point loops rolled.  The work of one point is still unrolled over
-  // modes and variables, with table rows from Rt (scalar loads); the face
-  // traces go through the tangential coefficients of the face (face_modes).
-  // This bounds code size, compile time and live registers.
-  static constexpr bool BIG = (M * V >= 100);
+  // Large spaces (3D Q^2 and P^3 Euler: 27 or 20 modes x 5 variables; 3D
+  // Q^3: 64 modes) keep their point loops rolled.  The work of one point is
+  // still unrolled over modes and variables, with table rows from Rt (scalar
+  // loads); the face traces go through the tangential coefficients of the
+  // face (face_modes).  This bounds code size, compile time and live
+  // registers.
+  static constexpr bool BIG = (M * V >= 100) || M >= 64;
   static constexpr int UQ = BIG ? 1 : S::NQ;    // unroll of volume-point loops
   static constexpr int US = BIG ? 1 : NS;       // unroll of S_K loops
   static constexpr int TM = S::TM;

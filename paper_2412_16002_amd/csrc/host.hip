@@ -20,7 +20,7 @@ using namespace crkdg;
 namespace {
 
 using Registry = int (*)(const VariantOps**);
-const Registry kRegistries[] = {&variants_v1d, &variants_v2d_q_adv, &variants_v2d_p_adv, &variants_v2d_q12_euler, &variants_v2d_q3_euler, &variants_v2d_p_euler, &variants_v3d_q1, &variants_v3d_q2_adv, &variants_v3d_q2_euler, &variants_v3d_p, &variants_v3d_p2_euler, &variants_v3d_p3_euler, &variants_swe_1d_q, &variants_swe_2d_p};
+const Registry kRegistries[] = {&variants_v1d, &variants_v2d_q_adv, &variants_v2d_p_adv, &variants_v2d_q12_euler, &variants_v2d_q3_euler, &variants_v2d_p_euler, &variants_v3d_q1, &variants_v3d_q2_adv, &variants_v3d_q2_euler, &variants_v3d_p, &variants_v3d_p2_euler, &variants_v3d_p3_euler, &variants_v3d_q3_euler, &variants_v3d_k3_adv, &variants_swe_1d_q, &variants_swe_2d_p};
 
 thread_local std::string g_err = "";
 

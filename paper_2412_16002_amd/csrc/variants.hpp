@@ -117,6 +117,8 @@ int variants_v3d_q2_euler(const VariantOps** out);
 int variants_v3d_p(const VariantOps** out);
 int variants_v3d_p2_euler(const VariantOps** out);
 int variants_v3d_p3_euler(const VariantOps** out);
+int variants_v3d_q3_euler(const VariantOps** out);
+int variants_v3d_k3_adv(const VariantOps** out);
 int variants_swe_1d_q(const VariantOps** out);
 int variants_swe_2d_p(const VariantOps** out);
 

@@ -47,7 +47,7 @@ def _states(mesh, coeffs):
 
 
 FINAL_CASES = ["euler2d_q1_outflow", "euler2d_q2", "euler2d_q3", "euler2d_p1", "euler2d_p2", "euler3d_q1",
-               "euler3d_p1", "euler3d_q2", "euler3d_p2", "euler3d_p3", "burgers1d_p2", "euler1d_p3_outflow"]
+               "euler3d_p1", "euler3d_q2", "euler3d_p2", "euler3d_p3", "euler3d_q3", "burgers1d_p2", "euler1d_p3_outflow"]
 
 
 @pytest.mark.parametrize("alpha", ["point", "global"])

@@ -69,6 +69,12 @@ CASES = {
     "euler3d_p3_sides": dict(dim=3, n=(19, 5, 3), system="euler", k=3, space="P", stages=4, cfl=0.09,
                              bc=("periodic", "reflect", "dirichlet"), bc_upper=("periodic", "reflect", "outflow"),
                              bc_state={4: _cons(1.1, [0.1, 0.0, 0.3], 0.9)}),
+    "euler3d_q3_sides": dict(dim=3, n=(19, 5, 3), system="euler", k=3, stages=4, cfl=0.09,
+                             bc=("reflect", "dirichlet", "periodic"), bc_upper=("outflow", "reflect", "periodic"),
+                             bc_state={2: _cons(0.9, [0.2, 0.1, -0.3], 1.2)}),
+    "adv3d_q3_inflow": dict(dim=3, n=(19, 5, 3), system="advection", k=3, stages=4, vel=(1.0, -0.5, 0.3),
+                            bc=("dirichlet", "periodic", "outflow"), bc_upper=("outflow", "periodic", "dirichlet"),
+                            bc_state={0: [1.6], 5: [0.4]}, bound_lo=0.0, bound_hi=2.0, cfl=0.09),
     "euler2d_q3_walls": dict(dim=2, n=(13, 11), system="euler", k=3, stages=4, cfl=0.09,
                              bc=("reflect", "dirichlet"), bc_upper=("outflow", "reflect"),
                              bc_state={2: _cons(0.7, [0.1, 0.2], 0.6)}),

@@ -61,6 +61,11 @@ CASES = {
     # ragged), ragged along y and z
     "euler3d_p2": dict(dim=3, n=(19, 5, 3), system="euler", k=2, space="P", stages=3, cfl=0.15),
     "euler3d_p3": dict(dim=3, n=(19, 5, 3), system="euler", k=3, space="P", stages=4, cfl=0.09),
+    "euler3d_q3": dict(dim=3, n=(19, 5, 3), system="euler", k=3, stages=4, cfl=0.09),
+    "adv3d_p3": dict(dim=3, n=(19, 5, 3), system="advection", k=3, space="P", stages=4, vel=(1.0, 0.5, -0.3),
+                     bound_lo=0.0, bound_hi=2.0, cfl=0.09),
+    "adv3d_q3": dict(dim=3, n=(19, 5, 3), system="advection", k=3, stages=4, vel=(-0.6, 1.1, 0.4),
+                     bound_lo=0.0, bound_hi=2.0, cfl=0.09),
 }
 FP64_TOL = 1e-12
 
@@ -130,7 +135,7 @@ def test_stage_parity(lib, name):
 
 @pytest.mark.parametrize("name", ["burgers1d_p2", "euler1d_p3_outflow", "euler2d_q2", "euler2d_p3",
                                   "adv2d_q2", "euler3d_q1", "euler3d_q2", "euler3d_p1", "adv3d_p2",
-                                  "euler3d_p2", "euler3d_p3"])
+                                  "euler3d_p2", "euler3d_p3", "euler3d_q3", "adv3d_q3"])
 def test_step_parity(lib, name):
     """Three accepted steps through the device controller (adaptive dt from
     the fused wave-speed maximum) against the oracle's steps."""
@@ -158,7 +163,7 @@ def test_step_parity(lib, name):
 
 
 @pytest.mark.parametrize("name", ["burgers1d_p2", "euler1d_p3_outflow", "euler2d_q2", "euler2d_p2",
-                                  "euler3d_q1", "euler3d_q2", "euler3d_p2", "euler3d_p3"])
+                                  "euler3d_q1", "euler3d_q2", "euler3d_p2", "euler3d_p3", "euler3d_q3"])
 def test_cfl_and_averages(lib, name):
     params, o, mesh = _setup(lib, name)
     C = random_state(o, seed=41, rel_amp=0.1)
@@ -179,7 +184,7 @@ def test_cfl_and_averages(lib, name):
 
 
 @pytest.mark.parametrize("name", ["burgers1d_p2", "euler2d_q2", "euler2d_p3", "adv3d_q2", "euler3d_q2",
-                                  "euler3d_p3"])
+                                  "euler3d_p3", "euler3d_q3", "adv3d_p3"])
 def test_projection_parity(lib, name):
     params, o, mesh = _setup(lib, name)
 
@@ -204,7 +209,8 @@ def test_projection_parity(lib, name):
 
 
 @pytest.mark.parametrize("name", ["euler2d_q2", "euler2d_p3", "euler1d_p3_outflow", "burgers1d_p2",
-                                  "euler3d_q2", "euler3d_p1", "adv3d_p2", "euler3d_p2", "euler3d_p3"])
+                                  "euler3d_q2", "euler3d_p1", "adv3d_p2", "euler3d_p2", "euler3d_p3",
+                                  "euler3d_q3", "adv3d_p3", "adv3d_q3"])
 def test_mixed_stage_parity(lib, name):
     """Mixed precision (modes >= 1 and transforms in FP32, averages FP64): one
     stage from identical (FP32-representable) inputs within 1e-5 of the

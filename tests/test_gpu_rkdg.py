@@ -45,7 +45,7 @@ def _states(mesh, coeffs):
 
 STAGE_CASES = ["burgers1d_p2", "euler1d_p3_outflow", "euler1d_p1", "euler2d_q2", "euler2d_q1_outflow",
                "euler2d_q3", "euler2d_p3", "adv2d_q2", "euler3d_q1", "adv3d_q2", "euler3d_q2", "euler3d_p2",
-               "euler3d_p3"]
+               "euler3d_p3", "euler3d_q3", "adv3d_q3"]
 
 
 @pytest.mark.parametrize("name", STAGE_CASES)
