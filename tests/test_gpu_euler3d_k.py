@@ -47,7 +47,7 @@ def test_mixed_step_parity(lib, name):
     U = o.from_legendre(C0)
     t = 0.0
     for n in range(3):
-        _say(f"[3D P mixed step] {name} step {n}")
+        _say(f"[3D mixed step] {name} step {n}")
         U, info_o = o.step(U, t)
         t = info_o["t"]
         info = mesh.step(slots, ctl)[0]
