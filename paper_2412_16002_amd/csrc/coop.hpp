@@ -204,7 +204,11 @@ __device__ __forceinline__ void along2(const T (&x1)[ipow(N, ND)], const T (&x2)
   });
 }
 
-template <int D, int K, int SP, int SYS, typename T, int TX, int TY, int TZ>
+// KL = 1: the LDS layout of the inner stage with G (KIND 0), which shares no
+// face values between cells: per-cell face slots (64 cells instead of the
+// tile's faces), and where the volume goes through LDS by slabs (Q^3 in 3D)
+// the S_K values one Lobatto node at a time.
+template <int D, int K, int SP, int SYS, typename T, int TX, int TY, int TZ, int KL = 0>
 struct Coop {
   using S = Space<D, K, SP_Q>;    // the tensor space the arithmetic runs in
   using SS = Space<D, K, SP>;     // the stored space (Q^k, or P^k inside it)
@@ -235,13 +239,19 @@ struct Coop {
   static constexpr int nfd(int d) { return (tdim(d) + 1) * tsz1(d) * tsz2(d); }
   static constexpr int cmax(int a, int b) { return a > b ? a : b; }
   static constexpr int NF_MAX = cmax(cmax(nfd(0), nfd(1)), D == 3 ? nfd(2) : 0);
+  static constexpr bool LOCAL = KL == 1;
   // the volume point values of all variables go through LDS at once, or
-  // (when that would exceed 72 KiB: Q^3 in 3D, where it would leave room
-  // for one workgroup per CU or none) one slab of the last direction at a
-  // time
+  // (when that would exceed 72 KiB: Q^3 in 3D) one slab of the last
+  // direction at a time.  (Slabs for the 3D Q^2 G stage, with the S_K values
+  // by Lobatto node, took its LDS from 40 to 28 KB, room for four workgroups
+  // per CU instead of two or three, but the stage ran 9% slower: the slabs'
+  // barriers and the x-y values kept live cost more than the occupancy gave.)
   static constexpr bool SLAB = D == 3 && V * NQ * 64 * sizeof(T) > 72 * 1024;
   static constexpr int NQL = SLAB ? NQ / N : NQ;    // volume points per LDS pass
-  static constexpr int LDS_T = cmax(cmax(V * NQL * 64, V * NFP * 2 * NF_MAX), V * NPF * 64);
+  static constexpr int NLC = (LOCAL && SLAB) ? 1 : NL;  // Lobatto nodes of S_K per LDS pass
+  static constexpr int NPC = NLC * ipow(N, D - 1);  // S_K points per LDS pass
+  static constexpr int LDS_T = LOCAL ? cmax(cmax(V * NQL * 64, V * NFP * 2 * 64), V * NPC * 64)
+                                     : cmax(cmax(V * NQL * 64, V * NFP * 2 * NF_MAX), V * NPC * 64);
 
   // stored index of tensor mode m (exponents m % N, (m / N) % N, m / N^2),
   // -1 for a mode outside the stored space
@@ -398,6 +408,11 @@ struct Coop {
   template <int d>
   __device__ __forceinline__ static int fidx(int v, int b, int side, int fi) {
     return ((v * 2 + side) * nfd(d) + fi) * NFP + b;
+  }
+  // G (no value shared between cells): the traces of each cell's own lower
+  // (side 0) and upper (side 1) face, [v][side][b][lane]
+  __device__ __forceinline__ static int cidx(int v, int b, int side, int lane) {
+    return ((v * 2 + side) * NFP + b) * 64 + lane;
   }
 
   // ---- volume part of the weak form (Sec. 2.1): r += scale * volume residual
@@ -582,8 +597,13 @@ struct Coop {
       traces<d>(cm, lo, up);
 #pragma unroll
       for (int b = 0; b < NFP; ++b) {
-        lds(sm)[fidx<d>(g.v, b, 1, fi_lo)] = lo[b];
-        lds(sm)[fidx<d>(g.v, b, 0, fi_up)] = up[b];
+        if constexpr (DG) {
+          lds(sm)[fidx<d>(g.v, b, 1, fi_lo)] = lo[b];
+          lds(sm)[fidx<d>(g.v, b, 0, fi_up)] = up[b];
+        } else {
+          lds(sm)[cidx(g.v, b, 0, g.lane)] = lo[b];
+          lds(sm)[cidx(g.v, b, 1, g.lane)] = up[b];
+        }
       }
     }
     if constexpr (DG) {
@@ -700,15 +720,13 @@ struct Coop {
         const int cx = cl % TX, cy = (cl / TX) % TY, cz = cl / (TX * TY);
         const int lc[3] = {cx, cy, cz};
         if (lc[0] >= g.A[0] || lc[1] >= g.A[1] || lc[2] >= g.A[2]) continue;
-        const int fi = slot<d>(lc[d] + side, lc[oax1(d)], D == 3 ? lc[oax2(d)] : 0);
-        const int ss = side ? 0 : 1;
         T u[V];
 #pragma unroll
-        for (int w = 0; w < V; ++w) u[w] = lds(sm)[fidx<d>(w, b, ss, fi)];
+        for (int w = 0; w < V; ++w) u[w] = lds(sm)[cidx(w, b, side, cl)];
         T fu[V];
         P::flux(u, P::aux(u, I), d, I, fu);
 #pragma unroll
-        for (int w = 0; w < V; ++w) lds(sm)[fidx<d>(w, b, ss, fi)] = fu[w];
+        for (int w = 0; w < V; ++w) lds(sm)[cidx(w, b, side, cl)] = fu[w];
       }
     }
     __syncthreads();
@@ -718,8 +736,8 @@ struct Coop {
 #pragma unroll
       for (int b = 0; b < NFP; ++b) {
         // F: the face's flux (side 0 of the slot); G: the cell's own trace flux
-        flo[b] = lds(sm)[fidx<d>(g.v, b, DG ? 0 : 1, fi_lo)];
-        fup[b] = lds(sm)[fidx<d>(g.v, b, 0, fi_up)];
+        flo[b] = DG ? lds(sm)[fidx<d>(g.v, b, 0, fi_lo)] : lds(sm)[cidx(g.v, b, 0, g.lane)];
+        fup[b] = DG ? lds(sm)[fidx<d>(g.v, b, 0, fi_up)] : lds(sm)[cidx(g.v, b, 1, g.lane)];
       }
       const double sc = scale * I.rdx[d];
       // mode 0 in FP64, face by face in point order (the same sum in both cells)
@@ -819,13 +837,14 @@ struct Coop {
   }
 
   // ---- S_K values of one family (Lobatto nodes along fam, Gauss nodes
-  // along the others) of the output modes, into LDS
-  template <int fam>
+  // along the others) of the output modes, into LDS: the Lobatto nodes
+  // L0 .. L0 + NLC - 1 of the family
+  template <int fam, int L0>
   __device__ __forceinline__ static void sk_family(const Geo& g, const T (&oc)[M], Smem& sm) {
     auto ev = [](const T (&x)[N], T (&y)[N]) { O1::eval(x, y); };
     // Gauss nodes along the other directions first (N^D values), then the
-    // Lobatto nodes along fam: point p = (Lobatto index) + NL * (tangential
-    // point b, b over the other directions ascending)
+    // Lobatto nodes along fam: point p = (Lobatto index - L0) + NLC *
+    // (tangential point b, b over the other directions ascending)
     T t[M], u[M];
     if constexpr (D == 2) {
       along<N, 2, 1 - fam>(oc, t, ev);
@@ -836,7 +855,7 @@ struct Coop {
         for (int a = 0; a < N; ++a) line[a] = t[fam == 0 ? a + N * b : b + N * a];
         O1::eval_l(line, lv);
 #pragma unroll
-        for (int l = 0; l < NL; ++l) lds(sm)[(g.v * NPF + l + NL * b) * 64 + g.lane] = lv[l];
+        for (int l = 0; l < NLC; ++l) lds(sm)[(g.v * NPC + l + NLC * b) * 64 + g.lane] = lv[L0 + l];
       }
       (void)u;
     } else {
@@ -850,7 +869,7 @@ struct Coop {
         for (int a = 0; a < N; ++a) line[a] = u[(b % N) * s1 + (b / N) * s2 + a * sf];
         O1::eval_l(line, lv);
 #pragma unroll
-        for (int l = 0; l < NL; ++l) lds(sm)[(g.v * NPF + l + NL * b) * 64 + g.lane] = lv[l];
+        for (int l = 0; l < NLC; ++l) lds(sm)[(g.v * NPC + l + NLC * b) * 64 + g.lane] = lv[L0 + l];
       }
     }
   }
@@ -1035,15 +1054,16 @@ struct Coop {
           for (int d = 0; d < D; ++d) am[d] = fmax(am[d], P::speed(u, ax, d, I));
         }
       };
-      static_for<D>([&](auto FAM) {
-        constexpr int fam = decltype(FAM)::value;
-        sk_family<fam>(g, oc, sm);
+      static_for<D * (NL / NLC)>([&](auto FL) {
+        constexpr int fam = decltype(FL)::value / (NL / NLC);
+        constexpr int l0 = (decltype(FL)::value % (NL / NLC)) * NLC;
+        sk_family<fam, l0>(g, oc, sm);
         __syncthreads();
         if (g.active) {
-          for (int p = g.v; p < NPF; p += V) {
+          for (int p = g.v; p < NPC; p += V) {
             T u[V];
 #pragma unroll
-            for (int w = 0; w < V; ++w) u[w] = lds(sm)[(w * NPF + p) * 64 + g.lane];
+            for (int w = 0; w < V; ++w) u[w] = lds(sm)[(w * NPC + p) * 64 + g.lane];
             check(u);
           }
         }
@@ -1148,7 +1168,7 @@ constexpr int coop_waves_per_eu() {
 template <int D, int K, int SP, int SYS, typename T, int TX, int TY, int TZ, int KIND, bool BDY = false>
 __global__ __launch_bounds__((64 * Phys<D, SYS>::V)) __attribute__((amdgpu_waves_per_eu(
     coop_waves_per_eu<T, KIND>()))) void k_coop_stage(KArgs a) {
-  using C = Coop<D, K, SP, SYS, T, TX, TY, TZ>;
+  using C = Coop<D, K, SP, SYS, T, TX, TY, TZ, KIND == 0 ? 1 : 0>;
   __shared__ typename C::Smem sm;
   if (static_cast<int>(blockIdx.x) >= a.n_items) return;
   // the tile, the instance's constants and the controller's state are
