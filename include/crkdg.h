@@ -232,9 +232,8 @@ const char *crkdg_last_error(void);
  * upload them, and fill *layout.  Synchronous.  Errors: CRKDG_E_ARG for an
  * invalid problem, CRKDG_E_UNSUPPORTED for a combination not compiled,
  * CRKDG_E_HIP.  Compiled, each in FP64 and mixed form: 1D P^1-P^3 (all
- * systems); 2D Q^1-Q^3 and P^1-P^3 (advection, Euler); 3D Q^1 and P^1
- * (advection, Euler), Q^2 and P^2 advection, Q^2, P^2 and P^3 Euler.
- * Burgers is 1D only.  Shallow water: 1D P^1-P^3 and 2D Q^1-Q^3, P^1-P^3,
+ * systems); 2D Q^1-Q^3 and P^1-P^3 (advection, Euler); 3D Q^1-Q^3 and
+ * P^1-P^3 (advection, Euler).  Burgers is 1D only.  Shallow water: 1D P^1-P^3 and 2D Q^1-Q^3, P^1-P^3,
  * FP64 and mixed. */
 int crkdg_init_mesh(const crkdg_problem *problems, int32_t n_inst, crkdg_mesh **out,
                     crkdg_layout *layout);
