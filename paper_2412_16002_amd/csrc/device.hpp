@@ -1743,12 +1743,25 @@ __device__ __forceinline__ void stage_final_item(const KArgs& a, const BlockItem
   }
 }
 
+// Wavefronts per SIMD the register allocation of the one-thread final stage
+// aims at: in the mixed 2D kernels at least two (at most 256 registers; the
+// 2D P^3 Euler final stage took 272 and ran one wavefront per SIMD: 0.80 ms
+// against 0.61 ms at two with a few spills); in FP64 unconstrained (there
+// the limit spilled heavily: 1.13 -> 2.53 ms for the same stage), and in 3D
+// too (3D Q^1 Euler spilled 240 B per lane under it).
+template <int D, typename T>
+constexpr int final_waves_per_eu() {
+  return (sizeof(T) == 4 && D == 2) ? 2 : 1;
+}
+
 template <int D, int K, int SP, int SYS, typename T>
-__global__ __launch_bounds__(BLOCK) void k_stage_final(KArgs a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(final_waves_per_eu<D, T>()))) void
+k_stage_final(KArgs a) {
   if (static_cast<int>(blockIdx.x) < a.n_items) stage_final_item<D, K, SP, SYS, T>(a, a.bmap[blockIdx.x]);
 }
 template <int D, int K, int SP, int SYS, typename T>
-__global__ __launch_bounds__(BLOCK) void k_stage_final_p(KArgs a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(final_waves_per_eu<D, T>()))) void
+k_stage_final_p(KArgs a) {
   for (int it = blockIdx.x; it < a.n_items; it += gridDim.x) stage_final_item<D, K, SP, SYS, T>(a, a.bmap[it]);
 }
 
