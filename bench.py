@@ -25,7 +25,12 @@ More workloads are measured in the same run and reported under
                 states, per-instance dt;
   euler2d_rkdg  the 2D workload under the standard RKDG scheme (F in every
                 stage, same Butcher table and limiter), with the
-                cRKDG-over-RKDG step-time ratio.
+                cRKDG-over-RKDG step-time ratio;
+  euler3d_share8  one GPU's share of the headline mesh split into 8 z-slabs
+                (128 x 128 x 16 cells of the same width, periodic in z: the
+                slab's own opposite face stands in for the neighbour traces
+                of the one exchange per step; the wave's z frequency raised
+                to 8), throughput of that one GPU.
 
 Metric: DOF-stage updates/s = sum over instances of Nc M V x executed stages
 / wall time, with the state resident in HBM before the timed region starts.
@@ -61,10 +66,11 @@ def parse():
     ap.add_argument("--n", type=int, default=1024, help="cells per direction of the 2D workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
-    ap.add_argument("--workloads", default="euler2d,batched,euler2d_rkdg",
-                    help="extra workloads to measure (comma list of euler2d, batched, euler2d_rkdg; "
-                         "empty for none)")
-    ap.add_argument("--only", choices=["euler3d", "euler2d", "batched", "euler2d_rkdg"], default=None,
+    ap.add_argument("--workloads", default="euler2d,batched,euler2d_rkdg,euler3d_share8",
+                    help="extra workloads to measure (comma list of euler2d, batched, euler2d_rkdg, "
+                         "euler3d_share8; empty for none)")
+    ap.add_argument("--only", choices=["euler3d", "euler2d", "batched", "euler2d_rkdg", "euler3d_share8"],
+                    default=None,
                     help="run only this workload (mixed and FP64) and print its results (for profiling)")
     ap.add_argument("--alpha", choices=["face", "point", "global"], default="face",
                     help="Lax-Friedrichs alpha of every workload: per face (default), per face point, "
@@ -84,18 +90,21 @@ def state_bytes(nvars, nmodes, mixed):
 # ---------------------------------------------------------------------------
 # workload set-up (synthetic, seeded; state resident on the device)
 # ---------------------------------------------------------------------------
-def wave3d_state(mesh, state, case, n, torch):
+def wave3d_state(mesh, state, case, n, torch, nz=None, zfreq=1.0):
     """Samples of the smooth 3D wave at every volume Gauss point, made on the
-    device, projected by the library."""
+    device, projected by the library (n x n x nz cells of width 1/n; the
+    wave's z frequency zfreq)."""
+    nz = n if nz is None else nz
     xq = torch.from_numpy(mesh.points(0, 0)[:, :3]).cuda()
     Q = xq.shape[0]
     c = (torch.arange(n, device="cuda", dtype=torch.float64) + 0.5) / n
+    cz = (torch.arange(nz, device="cuda", dtype=torch.float64) + 0.5) / n
     h = 0.5 / n
     X = c.view(1, 1, n, 1) + h * xq[:, 0].view(1, 1, 1, Q)
     Y = c.view(1, n, 1, 1) + h * xq[:, 1].view(1, 1, 1, Q)
-    Z = c.view(n, 1, 1, 1) + h * xq[:, 2].view(1, 1, 1, Q)
-    rho = 1.0 + 0.99 * torch.sin(2.0 * math.pi * (X + Y + Z).reshape(-1, Q) + case.meta["phase"])
-    smp = torch.empty((5, n ** 3, Q), dtype=torch.float64, device="cuda")
+    Z = cz.view(nz, 1, 1, 1) + h * xq[:, 2].view(1, 1, 1, Q)
+    rho = 1.0 + 0.99 * torch.sin(2.0 * math.pi * (X + Y + zfreq * Z).reshape(-1, Q) + case.meta["phase"])
+    smp = torch.empty((5, n * n * nz, Q), dtype=torch.float64, device="cuda")
     for v in range(1, 4):
         smp[v] = rho
     smp[0] = rho
@@ -112,6 +121,9 @@ def setup(name, precision, crkdg, inputs, torch, n2d, alpha="face"):
             scheme = "rkdg"     # same workload, standard RKDG (F in every stage)
     elif name == "euler3d":
         cases = [inputs.euler_3d_wave(seed=0, n=128)]
+    elif name == "euler3d_share8":
+        # one GPU's share of the headline mesh split into 8 z-slabs
+        cases = [inputs.euler_3d_wave_slab(seed=0, n=128, parts=8)]
     else:
         cases = inputs.batched_2d(seed=0)
     probs = [crkdg.problem_from_params(dict(c.params, precision=precision, scheme=scheme, **extra))
@@ -120,6 +132,8 @@ def setup(name, precision, crkdg, inputs, torch, n2d, alpha="face"):
     slots = mesh.new_slots()
     if name == "euler3d":
         wave3d_state(mesh, slots[0], cases[0], 128, torch)
+    elif name == "euler3d_share8":
+        wave3d_state(mesh, slots[0], cases[0], 128, torch, nz=16, zfreq=8.0)
     else:
         for i, c in enumerate(cases):
             a, h = mesh.views(slots[0], inst=i)
@@ -190,7 +204,7 @@ def measure(name, precision, args, crkdg, inputs, torch, stream, kernels=True, b
     timed steps as two captured step graphs, one launch each)."""
     cases, mesh, slots, ctl = setup(name, precision, crkdg, inputs, torch, args.n, args.alpha)
     # launch shapes from the library's autotuner (results do not depend on them)
-    tuning = mesh.autotune(slots, ctl, reps=1 if name == "euler3d" else 2)
+    tuning = mesh.autotune(slots, ctl, reps=1 if name.startswith("euler3d") else 2)
     if batched:
         gw = mesh.graph(slots, ctl, attempts=args.warmup)
         gt = mesh.graph(slots, ctl, attempts=args.steps)

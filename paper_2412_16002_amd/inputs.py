@@ -155,6 +155,28 @@ def euler_3d_wave(seed=0, n=128, precision="mixed"):
                 meta=dict(phase=ph))
 
 
+def euler_3d_wave_slab(seed=0, n=128, parts=8, precision="mixed"):
+    """One GPU's share of the 3D wave workload when its n^3 mesh is split into
+    `parts` slabs along z: n x n x n/parts cells of the same width on
+    [0, 1]^2 x [0, 1/parts], periodic in z (the slab's own opposite face
+    stands in for the neighbour's traces of the exchange), the wave's z
+    frequency raised to `parts` so that the slab holds whole periods."""
+    rng = np.random.default_rng(seed)
+    ph = float(rng.uniform(0.0, 2.0 * np.pi))
+
+    def exact(x, t):
+        x = np.asarray(x)
+        s = x[..., 0] + x[..., 1] + parts * x[..., 2] - (2.0 + parts) * t
+        rho = 1.0 + 0.99 * np.sin(2.0 * np.pi * s + ph)
+        return conservative(rho, np.ones(x.shape[:-1] + (3,)), np.ones(x.shape[:-1]))
+
+    params = dict(dim=3, n=(n, n, n // parts), system="euler", k=2, space="Q", stages=4, cfl=0.153,
+                  eps=1e-8, bc=("periodic",) * 3, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0 / parts),
+                  precision=precision)
+    return Case("euler_3d_wave_slab", params, u0=lambda x: exact(x, 0.0), exact=exact,
+                meta=dict(phase=ph, parts=parts))
+
+
 def euler_3d_blast(seed=0, n=128, precision="mixed"):
     rng = np.random.default_rng(seed)
     c = rng.uniform(0.25, 0.75, 3)
