@@ -588,15 +588,15 @@ struct Coop {
     const int q2 = (D == 3) ? g.l[oax2(d)] : 0;
     const int fi_lo = slot<d>(g.l[d], q1, q2);
     const int fi_up = slot<d>(g.l[d] + 1, q1, q2);
-    // (0) the halo cell of this lane (at most one when 2 T1 T2 <= 64): its
-    // modes are loaded before the own traces are formed, so that the loads'
-    // latency overlaps that work
-    constexpr bool HONE = 2 * T1 * T2 <= 64;
+    // (0) the halo cell of this lane (the tile shapes used have at most 64
+    // halo cells per direction: one per lane): its modes are loaded before
+    // the own traces are formed, so that the loads' latency overlaps that work
+    static_assert(2 * T1 * T2 <= 64, "one halo cell per lane");
     T hm[M];
     double h0 = 0.0;
     bool hv = false;
     int hside = 0, hfi = 0;
-    if constexpr (DG && HONE) {
+    if constexpr (DG) {
       const int j = g.lane;
       if (j < 2 * T1 * T2) {
         const int side = j / (T1 * T2);
@@ -639,44 +639,12 @@ struct Coop {
       }
     }
     if constexpr (DG) {
-      if constexpr (HONE) {
-        if (hv) {
-          T lo[NFP], up[NFP];
-          traces<d>(hm, lo, up);
-          // the halo cell below the tile shows its upper trace, the one above its lower trace
+      if (hv) {
+        T lo[NFP], up[NFP];
+        traces<d>(hm, lo, up);
+        // the halo cell below the tile shows its upper trace, the one above its lower trace
 #pragma unroll
-          for (int b = 0; b < NFP; ++b) lds(sm)[fidx<d>(g.v, b, hside, hfi)] = hside ? lo[b] : up[b];
-        }
-      } else {
-        // halo traces of the cells across the tile boundary (periodic wrap
-        // included); a non-periodic mesh side is a ghost, formed in the flux pass
-#pragma unroll 1
-        for (int j = g.lane; j < 2 * T1 * T2; j += 64) {
-          const int side = j / (T1 * T2);
-          const int qq = j % (T1 * T2);
-          const int h1 = qq % T1, h2 = qq / T1;
-          if (h1 >= g.A[oax1(d)] || (D == 3 && h2 >= g.A[oax2(d)])) continue;
-          const int p = side ? g.A[d] : 0;
-          int hc[3] = {0, 0, 0};
-          hc[oax1(d)] = g.o[oax1(d)] + h1;
-          if (D == 3) hc[oax2(d)] = g.o[oax2(d)] + h2;
-          int x = g.o[d] + (side ? g.A[d] : -1);
-          if (x < 0 || x >= I.n[d]) {
-            if (I.bc[2 * d + side] != CRKDG_BC_PERIODIC) continue;
-            x = (x < 0) ? x + I.n[d] : x - I.n[d];
-          }
-          hc[d] = x;
-          const uint32_t hcell = static_cast<uint32_t>(hc[0] + I.n[0] * (hc[1] + I.n[1] * hc[2]));
-          T hm[M];
-          double h0;
-          load_var(avg, hi, I.ncell, hcell, g.v, hm, h0);
-          T lo[NFP], up[NFP];
-          traces<d>(hm, lo, up);
-          const int fi = slot<d>(p, h1, h2);
-          // the halo cell below the tile shows its upper trace, the one above its lower trace
-#pragma unroll
-          for (int b = 0; b < NFP; ++b) lds(sm)[fidx<d>(g.v, b, side, fi)] = side ? lo[b] : up[b];
-        }
+        for (int b = 0; b < NFP; ++b) lds(sm)[fidx<d>(g.v, b, hside, hfi)] = hside ? lo[b] : up[b];
       }
       // time-dependent Dirichlet data of a mesh side the tile touches: the
       // exterior values go into the ghost side of its boundary slots (side 0
