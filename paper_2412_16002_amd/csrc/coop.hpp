@@ -589,8 +589,10 @@ struct Coop {
     const int fi_lo = slot<d>(g.l[d], q1, q2);
     const int fi_up = slot<d>(g.l[d] + 1, q1, q2);
     // (0) the halo cell of this lane (the tile shapes used have at most 64
-    // halo cells per direction: one per lane): its modes are loaded before
-    // the own traces are formed, so that the loads' latency overlaps that work
+    // halo cells per direction: one per lane; periodic wrap included, while
+    // a non-periodic mesh side has none: its ghost is formed in the flux
+    // pass): its modes are loaded before the own traces are formed, so that
+    // the loads' latency overlaps that work
     static_assert(2 * T1 * T2 <= 64, "one halo cell per lane");
     T hm[M];
     double h0 = 0.0;
