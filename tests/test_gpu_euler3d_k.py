@@ -1,7 +1,8 @@
 """3D P^2, P^3 (total degree) and Q^3 Euler, FP64 and mixed precision,
 through the cooperative tensor kernels (P^k held inside Q^k): three
 controller steps of the mixed form against the FP64 oracle, and the exact
-density wave at three resolutions in both forms.  Stage, limiter, step, boundary, alpha and
+density wave at three resolutions in both forms, and blast runs with the
+limiter at work.  Stage, limiter, step, boundary, alpha and
 standard-RKDG parity of the same families run with the other families'
 (test_gpu_parity, test_gpu_mixed_parity, test_gpu_boundaries,
 test_gpu_alpha, test_gpu_rkdg)."""
@@ -13,6 +14,7 @@ import pytest
 
 import oracle
 from _helpers import gpu_problem, oracle_problem, random_state, rel_err_per_var, round_hi
+from paper_2412_16002_amd import inputs
 from test_gpu_parity import CASES
 
 pytestmark = pytest.mark.gpu
@@ -84,3 +86,39 @@ def test_density_wave_converges(lib, space, k, meshes, lo):
     # modes: 3e-8 of relative L1 on 32^3 Q^3, where the FP64 error is 1.5e-7)
     for ef, em in zip(errs["fp64"], errs["mixed"]):
         assert abs(em - ef) <= 0.05 * ef + 1e-7
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+@pytest.mark.parametrize("space,k", [("P", 2), ("P", 3), ("Q", 3)])
+def test_blast_runs(lib, space, k, precision):
+    """A 24^3 blast (p = 100 inside a seeded sphere, 1e-4 outside, rho = 1,
+    w = 0) through the cooperative kernels: 20 accepted steps of the device
+    controller (halvings allowed), totals conserved to 1e-12 of the largest,
+    and no S_K point outside B^eps in any cell (oracle check)."""
+    n = 24
+    case = inputs.euler_3d_blast(seed=0, n=n, precision=precision)
+    params = dict(case.params, precision=precision, k=k, space=space, stages=k + 1,
+                  cfl={2: 0.15, 3: 0.09}[k])
+    mesh = lib.Mesh(gpu_problem(params))
+    slots = mesh.new_slots()
+    a, h = mesh.views(slots[0])
+    a.copy_(torch.from_numpy(case.cell_states.T.copy()))
+    h.zero_()
+    ctl = mesh.new_ctl()
+    mesh.start(slots, ctl, t0=0.0)
+    T0 = mesh.totals(slots[0]).cpu().numpy()
+    halvings = 0
+    for _ in range(20):
+        info = mesh.step(slots, ctl)[0]
+        assert info["status"] == 0
+        halvings += info["halvings"]
+    T1 = mesh.totals(slots[info["cur"]]).cpu().numpy()
+    cons = np.abs(T1 - T0) / np.abs(T0).max()
+    o = oracle.CRKDG(oracle_problem(params))
+    U = o.from_legendre(mesh.get_legendre(slots[info["cur"]]))
+    viol = o.bound_violations(U)
+    _say(f"[blast 24^3] {space}{k} {precision}: t {info['t']:.3e}, halvings {halvings}, "
+         f"totals change {cons.max():.1e}, violations {viol}")
+    assert np.all(np.isfinite(U))
+    assert np.all(cons <= 1e-12)
+    assert viol == 0
