@@ -43,6 +43,24 @@ def test_separable_terms_reproduce_the_exact_data():
         cs = inputs.table1_advection(2, 0)
         sep1 = sum(g * G(X[:, :1]) for g, G in zip(_g(cs.meta["bc_coef"], t), cs.meta["bc_terms"]))
         assert np.allclose(sep1, cs.exact(np.zeros((50, 1)), t), rtol=1e-14, atol=1e-14)
+        # the 3D density wave with exact data on its x and y sides
+        cw = inputs.euler_wave_box3d(2, (4, 4, 4))
+        X3 = rng.uniform(0.0, 1.0, (50, 3))
+        sep3 = sum(g * G(X3) for g, G in zip(_g(cw.meta["bc_coef"], t), cw.meta["bc_terms"]))
+        assert np.allclose(sep3, cw.exact(X3, t), rtol=1e-14, atol=1e-14)
+
+
+def test_slab_share_input_is_periodic_over_the_slab():
+    """The one-GPU share of the 3D wave (a z-slab of the 128^3 mesh with the
+    wave's z frequency raised to the number of slabs) is periodic over the
+    slab, so the periodic slab stands in for its neighbours without a seam."""
+    cs = inputs.euler_3d_wave_slab(seed=0, n=16, parts=8)
+    assert tuple(cs.params["n"]) == (16, 16, 2) and cs.params["hi"][2] == 1.0 / 8
+    rng = np.random.default_rng(3)
+    X = rng.uniform(0.0, 1.0, (40, 3)) * np.array([1.0, 1.0, 1.0 / 8])
+    for t in (0.0, 0.3):
+        shifted = X + np.array([0.0, 0.0, 1.0 / 8])
+        assert np.allclose(cs.exact(X, t), cs.exact(shifted, t), rtol=1e-12, atol=1e-12)
 
 
 def _l2(o, U, exact, t):
