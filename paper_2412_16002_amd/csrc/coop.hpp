@@ -245,7 +245,8 @@ struct Coop {
   // direction at a time.  (Slabs for the 3D Q^2 G stage, with the S_K values
   // by Lobatto node, took its LDS from 40 to 28 KB, room for four workgroups
   // per CU instead of two or three, but the stage ran 9% slower: the slabs'
-  // barriers and the x-y values kept live cost more than the occupancy gave.)
+  // barriers and the x-y values kept live cost more than the occupancy gave;
+  // two passes with the modes loaded again for the second ran 18% slower.)
   static constexpr bool SLAB = D == 3 && V * NQ * 64 * sizeof(T) > 72 * 1024;
   static constexpr int NQL = SLAB ? NQ / N : NQ;    // volume points per LDS pass
   static constexpr int NLC = (LOCAL && SLAB) ? 1 : NL;  // Lobatto nodes of S_K per LDS pass
