@@ -241,13 +241,15 @@ struct Coop {
   static constexpr int NF_MAX = cmax(cmax(nfd(0), nfd(1)), D == 3 ? nfd(2) : 0);
   static constexpr bool LOCAL = KL == 1;
   // the volume point values of all variables go through LDS at once, or
-  // (when that would exceed 72 KiB: Q^3 in 3D) one slab of the last
-  // direction at a time.  (Slabs for the 3D Q^2 G stage, with the S_K values
+  // (when that would exceed 120 KiB: FP64 Q^3 in 3D) one slab of the last
+  // direction at a time.  (For mixed Q^3, 80 KiB at once, the slabs only
+  // added barriers: the face slots keep it at one workgroup per CU either
+  // way; 19.3 against 18.8 ms per step on 96^3.)  (Slabs for the 3D Q^2 G stage, with the S_K values
   // by Lobatto node, took its LDS from 40 to 28 KB, room for four workgroups
   // per CU instead of two or three, but the stage ran 9% slower: the slabs'
   // barriers and the x-y values kept live cost more than the occupancy gave;
   // two passes with the modes loaded again for the second ran 18% slower.)
-  static constexpr bool SLAB = D == 3 && V * NQ * 64 * sizeof(T) > 72 * 1024;
+  static constexpr bool SLAB = D == 3 && V * NQ * 64 * sizeof(T) > 120 * 1024;
   static constexpr int NQL = SLAB ? NQ / N : NQ;    // volume points per LDS pass
   static constexpr int NLC = (LOCAL && SLAB) ? 1 : NL;  // Lobatto nodes of S_K per LDS pass
   static constexpr int NPC = NLC * ipow(N, D - 1);  // S_K points per LDS pass
